@@ -1,0 +1,95 @@
+"""Block inner product and intra-orthogonalization muscles (oracle, FP64).
+
+Test infrastructure only: see the package docstring.
+
+Real arithmetic throughout, so the conjugate transpose of the paper is the
+plain transpose.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def ip(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """Classical block inner product <X, Y> = X^T Y (Sec. 2.2, Table 1)."""
+    return X.T @ Y
+
+
+def chol_flag(Om: np.ndarray):
+    """Cholesky factor with a breakdown flag (Sec. 4, the ``chol`` variant that
+    raises the NaN-flag instead of failing).
+
+    Returns (R, ok) with R upper triangular and R^T R = Om, computed from the
+    upper triangle of Om by the unblocked column-by-column recurrence.
+
+    Reading: the flag is raised iff some pivot Om_jj - sum_{i<j} R_ij^2 is
+    not a positive finite number (the paper speaks of a matrix that is
+    numerically not positive definite; no further threshold is applied).
+    On a flag the returned R is incomplete and must not be used.
+    """
+    Om = np.asarray(Om, dtype=np.float64)
+    s = Om.shape[0]
+    R = np.zeros((s, s))
+    for j in range(s):
+        d = Om[j, j] - R[:j, j] @ R[:j, j]
+        if not np.isfinite(d) or d <= 0.0:
+            return R, False
+        R[j, j] = math.sqrt(d)
+        if j + 1 < s:
+            R[j, j + 1:] = (Om[j, j + 1:] - R[:j, j] @ R[:j, j + 1:]) / R[j, j]
+    return R, True
+
+
+def right_solve_upper(X: np.ndarray, R: np.ndarray) -> np.ndarray:
+    """X R^{-1} for upper-triangular R (a triangular solve, not an inverse)."""
+    return sla.solve_triangular(R, X.T, trans="T", lower=False, check_finite=False).T
+
+
+def left_solve_upper_t(R: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """R^{-T} X for upper-triangular R."""
+    return sla.solve_triangular(R, X, trans="T", lower=False, check_finite=False)
+
+
+def cholqr(X: np.ndarray):
+    """CholQR muscle (Sec. 2.3 and the list of muscles in Sec. 5):
+    G = X^T X (one sync), R = chol(G) with flag, Q = X R^{-1}.
+    Returns (Q, R, ok)."""
+    G = ip(X, X)
+    R, ok = chol_flag(G)
+    if not ok:
+        return None, R, False
+    return right_solve_upper(X, R), R, True
+
+
+def houseqr(X: np.ndarray):
+    """HouseQR muscle: Householder QR (LAPACK via numpy), the unconditionally
+    stable muscle of Sec. 4.
+
+    Reading: the signs are fixed so that diag(R) >= 0 (a zero diagonal entry
+    gets sign +1), which makes the factorization unique for full-rank X.
+    The flag is raised only for an exactly zero or non-finite diagonal."""
+    Q, R = np.linalg.qr(X, mode="reduced")
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    Q = Q * d
+    R = d[:, None] * R
+    ok = bool(np.all(np.isfinite(R)) and np.all(np.diag(R) != 0.0))
+    return Q, R, ok
+
+
+def intra_ortho(X: np.ndarray, muscle: str):
+    """IntraOrtho(X) -> (Q, R, T, ok).  T is the auxiliary factor the
+    SVL/LTS skeletons expect from the muscle (Alg. 5, lines 2 and 7).
+
+    Reading: CholQR and HouseQR carry no such factor; T = I_s, its value for
+    an exactly orthonormal Q."""
+    if muscle == "cholqr":
+        Q, R, ok = cholqr(X)
+    elif muscle == "houseqr":
+        Q, R, ok = houseqr(X)
+    else:
+        raise ValueError(f"unknown muscle {muscle!r}")
+    return Q, R, np.eye(X.shape[1]), ok

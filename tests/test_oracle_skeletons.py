@@ -1,0 +1,114 @@
+"""Pins for the oracle's block Arnoldi skeletons: invariants fixed by the
+mathematics (Arnoldi relation, exact-arithmetic equality of skeletons,
+closed-form spectrum)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from oracle.skeletons import Counters, make_skeleton
+from paper_2208_09899_amd import workloads as w
+
+STABLE = ["bmgs", "bmgs_svl", "bmgs_lts", "bmgs_cwy", "bmgs_icwy", "bcgsi_ls"]
+ALL = STABLE + ["bcgs_pip"]
+
+
+def _cycle(name, A, B, m, muscle="cholqr"):
+    sk = make_skeleton(name, A, B.shape[1], m, muscle, Counters())
+    last = 0
+    for j in sk.run(B):
+        last = j
+    return sk, last
+
+
+@pytest.mark.parametrize("muscle", ["cholqr", "houseqr"])
+@pytest.mark.parametrize("name", ALL)
+@pytest.mark.parametrize("case", ["lap1d", "lap2d", "convdiff"])
+def test_block_arnoldi_relation(name, muscle, case):
+    """A V_j = V_{j+1} H_{1:j+1,1:j} (Sec. 2.4, eq. block_arnoldi) to 1e-12."""
+    if case == "lap1d":
+        A, B, m = w.laplace_1d(1000).to_scipy(), w.rhs(1000, 4, 1), 20
+    elif case == "lap2d":
+        A, B, m = w.laplace_2d(32).to_scipy(), w.rhs(1024, 8, 2), 30
+    else:
+        A, B, m = w.convdiff_2d(40, 7.0, 0.8).to_scipy(), w.rhs(1600, 3, 9), 25
+    sk, j = _cycle(name, A, B, m, muscle)
+    assert j >= m - 1
+    s = B.shape[1]
+    Vj, Vj1 = sk.Vcat(j), sk.Vcat(j + 1)
+    AV = A @ Vj
+    rel = np.linalg.norm(AV - Vj1 @ sk.Hm1m(j)) / np.linalg.norm(AV)
+    assert rel <= 1e-12, rel
+    # the subdiagonal blocks are upper triangular Cholesky / R factors
+    for k in range(1, j + 1):
+        Hs = sk.H[k * s:(k + 1) * s, (k - 1) * s:k * s]
+        assert np.allclose(np.tril(Hs, -1), 0.0)
+        assert np.all(np.diag(Hs) > 0)
+    # the first block of the basis spans B: B = V_1 Beta
+    assert np.linalg.norm(sk.V[0] @ sk.Beta - B) <= 1e-13 * np.linalg.norm(B)
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_skeletons_agree_in_exact_arithmetic(name):
+    """All classical skeletons generate the same block QR, hence the same V and
+    H (Sec. 2.4.2 remark); compared with textbook BMGS on the first columns of a
+    well-conditioned problem."""
+    A = (w.laplace_2d(24).to_scipy() + 3.0 * sp.identity(576)).tocsr()
+    B = w.rhs(576, 4, 5)
+    ref, _ = _cycle("bmgs", A, B, 8)
+    sk, j = _cycle(name, A, B, 8)
+    assert j == 8
+    # BCGS-PIP's loss of orthogonality grows like eps * kappa^2 of the Krylov
+    # basis (Table 2), which here gains about a factor 10 per block column.
+    tol = 1e-6 if name == "bcgs_pip" else 1e-10
+    assert np.linalg.norm(sk.Hm1m(8) - ref.Hm1m(8)) <= tol * np.linalg.norm(ref.Hm1m(8))
+    assert np.linalg.norm(sk.Vcat(9) - ref.Vcat(9)) <= tol * 3
+
+
+@pytest.mark.parametrize("name", ALL)
+@pytest.mark.parametrize("n,s,m", [(64, 4, 16), (32, 4, 8)])
+def test_hessenberg_spectrum_closed_form(name, n, s, m):
+    """With n = m s the block Krylov space is the whole space, so H_m is similar
+    to A = tridiag(-1,2,-1), whose eigenvalues are 2 - 2 cos(j pi/(n+1))."""
+    A = w.laplace_1d(n).to_scipy()
+    B = w.rhs(n, s, 11)
+    sk, _ = _cycle(name, A, B, m)
+    Hm = sk.H[: m * s, : m * s]
+    ev = np.sort(np.linalg.eigvals(Hm).real)
+    exact = np.sort(2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
+    tol = 1e-7 if name == "bcgs_pip" else 1e-10     # PIP: O(eps kappa^2) loss of orthogonality
+    assert np.max(np.abs(ev - exact)) <= tol
+
+
+def test_delayed_skeletons_flag_two_columns_back():
+    """A forced Cholesky flag at loop step k leaves k-2 final columns in the
+    delayed skeletons (Algs. 6, 7) and k-1 in the others."""
+    A = w.laplace_1d(300).to_scipy()
+    B = w.rhs(300, 2, 3)
+    for name in ALL:
+        sk = make_skeleton(name, A, 2, 10, "cholqr", Counters(), force_steps={5})
+        cols = list(sk.run(B))
+        expect = 3 if sk.delayed else 4
+        assert sk.flagged and sk.last == expect and cols == list(range(1, expect + 1))
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_counters_per_cycle(name):
+    """Per-cycle A-calls / basis applications / syncs of a full cycle of j
+    columns, as implied by the appendix tables (Sec. 5 and Appendix A)."""
+    A = w.laplace_1d(500).to_scipy()
+    B = w.rhs(500, 3, 4)
+    ct = Counters()
+    sk = make_skeleton(name, A, 3, 12, "cholqr", ct)
+    j = len(list(sk.run(B)))
+    assert j == 12
+    expect = {
+        "bmgs": (j, 2 * j, j * (j + 1) // 2 + j + 1),
+        "bcgs_pip": (j, 3 * j, j + 1),
+        "bmgs_svl": (j, 3 * j, 3 * j + 1),
+        "bmgs_lts": (j, 3 * j, 3 * j + 1),
+        "bmgs_cwy": (j + 1, 3 * j + 1, j + 2),
+        "bmgs_icwy": (j + 1, 3 * j + 1, j + 2),
+        "bcgsi_ls": (j + 1, 4 * j + 1, j + 2),
+    }[name]
+    assert ct.as_tuple() == expect

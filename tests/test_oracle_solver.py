@@ -1,0 +1,238 @@
+"""Pins for the oracle's restarted BFOM / BGMRES driver: the paper's printed
+integers, dense LU, textbook GMRES and CG for s = 1, monotone BGMRES
+residuals, Theorem 1, and the adaptive-restart path."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from paper_2208_09899_amd import workloads as w
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+STABLE = ["bmgs_svl", "bmgs_lts", "bmgs_cwy", "bmgs_icwy", "bcgsi_ls"]
+
+
+def _golden():
+    with open(os.path.join(HERE, "golden", "paper_tridiag_table.json")) as f:
+        return json.load(f)
+
+
+def test_paper_tridiag_counts_match_printed_table():
+    """Run the paper's tridiag configuration for exactly the printed number of
+    iterations; A-calls, basis applications and syncs must equal the
+    appendix table."""
+    g = _golden()
+    A, B = w.tridiag_paper(1000)
+    A = A.to_scipy()
+    for row in g["rows"]:
+        name, cycles, iters, a, v, syn = row
+        sk = g["skeleton_of"][name]
+        r = oracle.solve(A, B, "fom", sk, "cholqr", m=70, tol=0.0, max_cycles=10, max_iters=iters)
+        assert r.iters == iters
+        assert len(r.cycle_len) == cycles, (name, r.cycle_len)
+        assert r.counts == (a, v, syn), (name, r.counts)
+
+
+@pytest.mark.parametrize("sk", ["bmgs", "bmgs_cwy", "bmgs_icwy", "bcgsi_ls"])
+def test_paper_tridiag_convergence_profile(sk):
+    """With the paper's stopping rule (relative error against the direct
+    solution, tol 1e-10), the stable skeletons run one full cycle of 70 and
+    finish in the second.  The paper prints 24 columns for the second cycle;
+    this oracle needs 25 (the error at column 24 is 1.19e-10)."""
+    A, B = w.tridiag_paper(1000)
+    A = A.to_scipy()
+    xs = np.linalg.solve(A.toarray(), B)
+    r = oracle.solve(A, B, "fom", sk, "cholqr", m=70, tol=1e-10, max_cycles=10, x_star=xs)
+    assert r.status == "ok"
+    assert r.cycle_len[0] == 70 and len(r.cycle_len) == 2
+    assert r.cycle_len[1] in (24, 25)
+
+
+@pytest.mark.parametrize("method", ["fom", "gmres"])
+@pytest.mark.parametrize("sk", STABLE)
+@pytest.mark.parametrize("kind,n", [("spd", 60), ("nonsym", 150), ("spd", 200)])
+def test_restarted_solve_matches_dense_lu(method, sk, kind, n):
+    A = w.random_dense_operator(n, seed=n, kind=kind).to_scipy()
+    B = w.rhs(n, 3, 100 + n)
+    Ad = A.toarray()
+    X_lu = np.linalg.solve(Ad, B)
+    tol = 1e-12
+    r = oracle.solve(A, B, method, sk, "cholqr", m=10, tol=tol, max_cycles=500)
+    assert r.status == "ok", (r.status, r.iters)
+    kappa = np.linalg.cond(Ad)
+    err = np.linalg.norm(r.X - X_lu) / np.linalg.norm(X_lu)
+    assert err <= 10 * kappa * tol, (err, kappa)
+    true_res = np.linalg.norm(B - Ad @ r.X) / np.linalg.norm(B)
+    assert true_res <= 10 * tol
+
+
+@pytest.mark.parametrize("sk", STABLE + ["bmgs"])
+def test_bgmres_residual_estimates_are_monotone(sk):
+    """BGMRES minimizes the residual over a growing space within a cycle, and
+    a restart starts from the current residual: the estimates never increase."""
+    wl = w.workload("tridiag1000")
+    r = oracle.solve(wl.A.to_scipy(), wl.B, "gmres", sk, "cholqr", m=20, tol=1e-8, max_cycles=8)
+    h = np.array(r.res_hist)
+    assert np.all(h[1:] <= h[:-1] * (1 + 1e-12))
+
+
+@pytest.mark.parametrize("method", ["fom", "gmres"])
+@pytest.mark.parametrize("sk", ["bcgsi_ls", "bmgs_cwy", "bmgs_svl"])
+def test_cospatial_residual_relation(method, sk):
+    """Theorem 1: B - A X_j = U_j (E_j^T Xi_j), and its norm is the estimate."""
+    A = w.laplace_2d(24).to_scipy()
+    B = w.rhs(576, 4, 7)
+    r = oracle.solve(A, B, method, sk, "cholqr", m=8, tol=1e-9, max_cycles=6, keep_cycles=True)
+    nB = np.linalg.norm(B)
+    pos = 0
+    for cyc in r.cycles:
+        pos += cyc["j"]
+        if "U" not in cyc:
+            continue
+        R = B - A @ cyc["X"]
+        assert np.linalg.norm(R - cyc["U"] @ cyc["C_next"]) <= 1e-9 * nB
+        assert abs(np.linalg.norm(R) / nB - r.res_hist[pos - 1]) <= 1e-9
+
+
+def _textbook_gmres(A, b, m, cycles):
+    """Restarted GMRES(m) with modified Gram-Schmidt Arnoldi and Givens
+    rotations, restarted from the explicit residual (Saad, Alg. 6.9)."""
+    n = b.shape[0]
+    x = np.zeros(n)
+    hist = []
+    nb = np.linalg.norm(b)
+    for _ in range(cycles):
+        r = b - A @ x
+        beta = np.linalg.norm(r)
+        V = np.zeros((n, m + 1)); H = np.zeros((m + 1, m))
+        V[:, 0] = r / beta
+        cs = np.zeros(m); sn = np.zeros(m)
+        g = np.zeros(m + 1); g[0] = beta
+        for j in range(m):
+            wv = A @ V[:, j]
+            for i in range(j + 1):
+                H[i, j] = V[:, i] @ wv
+                wv = wv - H[i, j] * V[:, i]
+            H[j + 1, j] = np.linalg.norm(wv)
+            V[:, j + 1] = wv / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            d = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / d, H[j + 1, j] / d
+            H[j, j] = d; H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]; g[j] = cs[j] * g[j]
+            hist.append(abs(g[j + 1]) / nb)
+        y = np.linalg.solve(np.triu(H[:m, :m]), g[:m])
+        x = x + V[:, :m] @ y
+    return np.array(hist), x
+
+
+@pytest.mark.parametrize("sk", STABLE + ["bmgs"])
+def test_s1_bgmres_is_textbook_gmres(sk):
+    A = w.convdiff_2d(12, 6.0, 1.1).to_scipy()
+    b = w.rhs(144, 1, 21)
+    ref, xref = _textbook_gmres(A, b[:, 0], 15, 3)
+    r = oracle.solve(A, b, "gmres", sk, "cholqr", m=15, tol=0.0, max_cycles=3)
+    h = np.array(r.res_hist)
+    assert h.shape == ref.shape
+    assert np.all(np.abs(h - ref) <= 1e-9 * ref + 1e-15)
+    assert np.linalg.norm(r.X[:, 0] - xref) <= 1e-9 * np.linalg.norm(xref)
+
+
+def _cg_residuals(A, b, k):
+    x = np.zeros_like(b); r = b.copy(); p = r.copy(); out = []
+    for _ in range(k):
+        Ap = A @ p
+        a = (r @ r) / (p @ Ap)
+        x = x + a * p
+        rn = r - a * Ap
+        out.append(np.linalg.norm(rn) / np.linalg.norm(b))
+        p = rn + ((rn @ rn) / (r @ r)) * p
+        r = rn
+    return np.array(out)
+
+
+@pytest.mark.parametrize("sk", STABLE)
+def test_s1_bfom_matches_cg_on_spd(sk):
+    """For SPD A and s = 1, the FOM residual after j steps equals the CG residual."""
+    A = (w.laplace_1d(100).to_scipy() + 0.05 * sp.identity(100)).tocsr()
+    b = w.rhs(100, 1, 22)
+    ref = _cg_residuals(A, b[:, 0], 25)
+    r = oracle.solve(A, b, "fom", sk, "cholqr", m=25, tol=0.0, max_cycles=1)
+    h = np.array(r.res_hist)
+    assert np.all(np.abs(h - ref) <= 1e-8 * ref)
+
+
+def test_bgmres_paper_form_equals_least_squares():
+    """The modified-BFOM coefficients (eq. Xm with the BGMRES modification)
+    solve min ||E_1 B C - H_{j+1,j} Xi||_F, and the estimate of eq. normF_Rm
+    is that minimum."""
+    rng = np.random.default_rng(0)
+    s, j = 3, 6
+    H = np.zeros(((j + 1) * s, j * s))
+    for k in range(j):
+        H[: (k + 1) * s, k * s:(k + 1) * s] = rng.standard_normal(((k + 1) * s, s))
+        H[(k + 1) * s:(k + 2) * s, k * s:(k + 1) * s] = np.triu(rng.standard_normal((s, s))) + 2 * np.eye(s)
+    BC = rng.standard_normal((s, s))
+    Xi, M, est = oracle.small_solve("gmres", H, BC, s)
+    g = np.zeros(((j + 1) * s, s)); g[:s] = BC
+    Xls = np.linalg.lstsq(H, g, rcond=None)[0]
+    assert np.linalg.norm(Xi - Xls) <= 1e-10 * np.linalg.norm(Xls)
+    assert abs(est - np.linalg.norm(g - H @ Xls)) <= 1e-10 * est
+    # FOM: square solve, estimate = ||H_{j+1,j} E_j^T Xi||_F
+    Xf, Mf, ef = oracle.small_solve("fom", H, BC, s)
+    assert np.allclose(Mf, 0)
+    assert np.linalg.norm(H[: j * s] @ Xf - g[: j * s]) <= 1e-10 * np.linalg.norm(BC)
+    assert abs(ef - np.linalg.norm(H[j * s:, (j - 1) * s:] @ Xf[(j - 1) * s:])) <= 1e-12 * ef
+
+
+@pytest.mark.parametrize("sk", STABLE)
+def test_forced_flag_adaptive_restart(sk):
+    """A Cholesky flag at (cycle 1, step 6) stops the cycle at its last final
+    column, restarts from it and shrinks m for good (Sec. 4)."""
+    A = w.laplace_2d(20).to_scipy()
+    B = w.rhs(400, 4, 8)
+    r = oracle.solve(A, B, "gmres", sk, "cholqr", m=10, tol=1e-10, max_cycles=200,
+                     force_flag=[(1, 6)])
+    delayed = sk in ("bmgs_cwy", "bmgs_icwy", "bcgsi_ls")
+    j1 = 4 if delayed else 5
+    assert r.cycle_len[0] == j1 and r.m_after[0] == j1
+    assert all(c <= j1 for c in r.cycle_len) and all(m == j1 for m in r.m_after)
+    assert r.status == "ok"
+    X_lu = np.linalg.solve(A.toarray(), B)
+    assert np.linalg.norm(r.X - X_lu) / np.linalg.norm(X_lu) <= 1e-7
+
+
+@pytest.mark.parametrize("sk,step", [("bcgsi_ls", 0), ("bcgsi_ls", 2), ("bmgs_cwy", 2),
+                                     ("bmgs_svl", 0), ("bmgs_svl", 1)])
+def test_breakdown_without_a_final_column(sk, step):
+    A = w.laplace_1d(200).to_scipy()
+    B = w.rhs(200, 2, 1)
+    r = oracle.solve(A, B, "gmres", sk, "cholqr", m=10, tol=1e-8, max_cycles=5,
+                     force_flag=[(1, step)])
+    assert r.status == "breakdown" and r.cycle_len == [0]
+    assert np.array_equal(r.X, np.zeros_like(B))
+
+
+def test_zero_rhs_and_rank_deficient_rhs():
+    A = w.laplace_1d(50).to_scipy()
+    r = oracle.solve(A, np.zeros((50, 2)), "gmres", "bcgsi_ls")
+    assert r.status == "ok" and r.iters == 0 and not r.X.any()
+    B = w.rhs(50, 3, 0)
+    B[:, 2] = 0.0
+    r = oracle.solve(A, B, "gmres", "bcgsi_ls")
+    assert r.status == "breakdown"
+
+
+def test_houseqr_muscle_end_to_end():
+    A = w.laplace_2d(16).to_scipy()
+    B = w.rhs(256, 4, 3)
+    r1 = oracle.solve(A, B, "gmres", "bcgsi_ls", "cholqr", m=10, tol=1e-10, max_cycles=100)
+    r2 = oracle.solve(A, B, "gmres", "bcgsi_ls", "houseqr", m=10, tol=1e-10, max_cycles=100)
+    assert r1.iters == r2.iters
+    assert np.linalg.norm(r1.X - r2.X) <= 1e-8 * np.linalg.norm(r1.X)
