@@ -1,0 +1,194 @@
+"""Benchmark: restarted block Krylov solves on one MI355X through the C ABI.
+
+Default workload: 2-D 5-point Dirichlet Laplacian on a 256 x 256 grid
+(n = 65536), s = 8 seeded N(0,1) right-hand sides, m = 30, tol 1e-8 on the
+relative residual estimate; one step = the six FP64 solves BFOM and BGMRES x
+{BCGSI+LS, BMGS-CWY, BMGS-ICWY} with CholQR.  value = solves per second.
+
+Prints one JSON line with the throughput, the block-Arnoldi GB/s, a roofline
+record for the dominant kernel class (algorithmic bytes over its HIP-event
+device time, measured live over the timed region) and the CPU oracle timed
+on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "block-Arnoldi GB/s + solves/s at rel. residual 1e-8; serving p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (workload key, scale, solve list [(method, skeleton)], precision, s, note)
+    "laplace2d": ("laplace2d", None,
+                  [(m, k) for k in ("bcgsi_ls", "bmgs_cwy", "bmgs_icwy") for m in ("fom", "gmres")],
+                  "fp64"),
+    "tridiag1000": ("tridiag1000", None, [("gmres", "bcgsi_ls")], "fp64"),
+    "rgg": ("rgg", None, [("gmres", "bcgsi_ls")], "fp64"),
+    "laplace3d": ("laplace3d", None, [("gmres", "bcgsi_ls")], "fp64"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, solves, gpu_iters, budget_s=15.0):
+    """Time the oracle on the host for a bounded number of block iterations of
+    the first configured solve and scale to solves/s with the GPU's (identical)
+    iteration counts."""
+    import threadpoolctl
+
+    import oracle
+    method, skel = solves[0]
+    A = wl.A.to_scipy()
+    # calibrate: a few iterations, then a sample sized to the budget
+    t0 = time.perf_counter()
+    oracle.solve(A, wl.B, method, skel, "cholqr", m=wl.m, tol=0.0, max_cycles=10 ** 6,
+                 max_iters=5)
+    t_cal = (time.perf_counter() - t0) / 5
+    k = int(max(10, min(2000, budget_s / max(t_cal, 1e-6))))
+    t0 = time.perf_counter()
+    r = oracle.solve(A, wl.B, method, skel, "cholqr", m=wl.m, tol=0.0, max_cycles=10 ** 6,
+                     max_iters=k)
+    dt = time.perf_counter() - t0
+    per_iter = dt / r.iters
+    step_s = per_iter * sum(gpu_iters)
+    threads = 1
+    for info in threadpoolctl.threadpool_info():
+        if info.get("internal_api") in ("openblas", "mkl", "blis"):
+            threads = max(threads, int(info.get("num_threads", 1)))
+    return {
+        "value": len(solves) / step_s,
+        "unit": "solves/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"{r.iters} block iterations of {method}/{skel} (m={wl.m}) in {dt:.1f} s "
+                   f"({per_iter * 1e3:.1f} ms/iteration), scaled by the GPU's iteration counts "
+                   f"{list(gpu_iters)}; NumPy/SciPy FP64, BLAS threads {threads}, "
+                   f"scipy.sparse SpMM single-threaded"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="laplace2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="do not record per-kernel HIP events in the timed region")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+              "the multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2208_09899_amd import lsba, workloads as w
+
+    key, scale, solves, precision = WORKLOADS[args.workload]
+    log(f"[bench] building workload {args.workload} ...")
+    wl = w.workload(key, scale)
+    n, s = wl.B.shape
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    B = torch.from_numpy(wl.B).to(dev)
+    X = torch.empty_like(B)
+    ctx = lsba.Context(0, stream="torch")
+    op = lsba.Operator(ctx, wl.A)
+    kw = dict(m=wl.m, tol=wl.tol, max_cycles=wl.max_cycles, precision=precision)
+
+    def step():
+        out = []
+        for method, skel in solves:
+            r = lsba.solve(ctx, op, B, X=X, method=method, skeleton=skel, **kw)
+            out.append((method, skel, r))
+        return out
+
+    for i in range(args.warmup):
+        log(f"[bench] warmup step {i + 1}/{args.warmup}")
+        step()
+    torch.cuda.synchronize()
+    if not args.no_timing:
+        ctx.set_timing(True)
+    log(f"[bench] timing {args.steps} steps of {len(solves)} solves")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for i in range(args.steps):
+        last = step()
+        log(f"[bench] step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = ctx.kernel_stats() if not args.no_timing else {}
+    elapsed = t1 - t0
+    nsolves = len(solves) * args.steps
+    value = nsolves / elapsed
+    res = []
+    for method, skel, r in last:
+        res.append({"method": method, "skeleton": skel, "status": r.status, "iters": r.iters,
+                    "cycles": len(r.cycle_len), "gpu_ms": round(r.gpu_ms, 3),
+                    "final_est": float(r.res_hist[-1]) if len(r.res_hist) else None})
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl.note, "n": n, "s": s, "m": wl.m, "tol": wl.tol,
+                   "solves_per_step": [f"{m}/{k}" for m, k in solves],
+                   "nnz": wl.A.nnz},
+        "solves": res,
+    }
+    if stats:
+        hot = ("spmm", "gram", "gram_reduce", "update")
+        tot_ms = sum(stats[k][1] for k in hot)
+        tot_b = sum(stats[k][2] for k in ("spmm", "gram", "update"))
+        line["arnoldi_gbps"] = tot_b / (tot_ms * 1e-3) / 1e9 if tot_ms else None
+        line["kernel_stats"] = {k: {"launches": v[0], "ms": round(v[1], 3),
+                                    "alg_GB": round(v[2] / 1e9, 4)} for k, v in stats.items()}
+        dom = max(("spmm", "gram", "update"), key=lambda k: stats[k][1])
+        launches, ms, by = stats[dom]
+        achieved = by / (ms * 1e-3) / 1e9 if ms else 0.0
+        line["roofline"] = {
+            "kernel": dom,
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": 1e3 * ms / launches if launches else None,
+            "alg_bytes_per_launch": by / launches if launches else None,
+        }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle sample ...")
+        line["cpu_baseline"] = cpu_baseline(wl, solves, [r["iters"] for r in res])
+    print(json.dumps(line), flush=True)
+    op.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * lsba.h -- C ABI of the MI355X (gfx950) adaptively restarted block Krylov
+ * solver library (liblsba.so).
+ *
+ * The library solves A X = B for a large sparse A (n x n, CSR) and a block of
+ * s right-hand sides (n x s) with restarted block FOM or block GMRES, built on
+ * a block Arnoldi cycle with one of the low-synchronization block Gram-Schmidt
+ * skeletons of K. Lund, "Adaptively restarted block Krylov subspace methods
+ * with low-synchronization skeletons":
+ *
+ *   - problem statement A X = B ........................... Sec. 2, eq. (AX=B)
+ *   - classical block inner product X^T Y ................. Sec. 2.2, Table 1
+ *   - skeletons BMGS-SVL / BMGS-LTS ....................... Sec. 3.2, Alg. 5
+ *   - skeletons BMGS-CWY / BMGS-ICWY ...................... Sec. 3.3, Alg. 6
+ *   - skeleton BCGSI+LS ................................... Sec. 3.4, Alg. 7
+ *   - muscles (IntraOrtho) CholQR / HouseQR ............... Sec. 2.3, Sec. 5
+ *   - BFOM / BGMRES as modified BFOM ...................... Sec. 2.4.1, eq. Xm
+ *   - cospatial restarts, residual estimate ............... Sec. 2.4.2, Thm. 1,
+ *                                                           eq. normF_Rm
+ *   - adaptive restarting on a Cholesky breakdown ......... Sec. 4
+ *   - loss of orthogonality ||I - V^T V||_2 ............... Sec. 2.3, eq. loo
+ *   - counts of A-calls, basis applications, syncs ........ Sec. 2.1, Sec. 5
+ *
+ * Real double-precision arithmetic (the conjugate transpose of the paper is
+ * the plain transpose).  Every step of the solve runs in the library's own
+ * HIP kernels on one GPU.
+ *
+ * Conventions
+ *   Layout.    Blocks of right-hand sides and solutions are n x s, row-major:
+ *              element (i, c) is at ptr[i * ld + c], ld >= s.
+ *   CSR.       row_ptr is int64 [n+1] with row_ptr[0] = 0 and row_ptr[n] = nnz,
+ *              non-decreasing; col_idx is int32 [nnz] with 0 <= col < n;
+ *              values is double [nnz].  Column order inside a row is free.
+ *   Memory.    Pointer arguments are host pointers when the matching
+ *              `on_device` argument is 0, and device pointers (on the
+ *              context's device) when it is 1.  Inputs stay owned by the
+ *              caller; the library copies what it keeps.  Handles are owned by
+ *              the caller and released only by their _destroy function.
+ *   Streams.   All device work of a context is issued on its stream.  Calls
+ *              on one context must come from one host thread at a time.
+ *   Errors.    A negative lsba_status means the call failed and wrote no
+ *              output; lsba_last_error() then holds a message.  A positive
+ *              status from lsba_solve means X holds the last iterate and the
+ *              result is valid.
+ *   Limits.    1 <= s <= 32, 1 <= m <= 128, n >= 1, n * s < 2^31.
+ */
+#ifndef LSBA_H
+#define LSBA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LSBA_OK = 0,                /* converged: residual estimate / ||B||_F <= tol            */
+  LSBA_NOT_CONVERGED = 1,     /* max_cycles or max_iters reached; X = last iterate         */
+  LSBA_BREAKDOWN = 2,         /* Cholesky flag with no final column left (Sec. 4); X kept  */
+  LSBA_ERR_ARG = -1,          /* invalid argument (null pointer, bad size, bad enum)      */
+  LSBA_ERR_OOM = -2,          /* device or host allocation failed                         */
+  LSBA_ERR_HIP = -3,          /* a HIP runtime call failed                                */
+  LSBA_ERR_UNSUPPORTED = -4,  /* valid but not supported combination                      */
+  LSBA_ERR_BUSY = -5          /* the serving queue is full                                */
+} lsba_status;
+
+typedef enum { LSBA_FOM = 0, LSBA_GMRES = 1 } lsba_method;       /* modification none / harmonic */
+
+typedef enum {
+  LSBA_BCGSI_LS = 0,          /* Alg. 7 */
+  LSBA_BMGS_SVL = 1,          /* Alg. 5, Schreiber-Van Loan T update */
+  LSBA_BMGS_LTS = 2,          /* Alg. 5, lower-triangular-solve T update */
+  LSBA_BMGS_CWY = 3,          /* Alg. 6, compact WY */
+  LSBA_BMGS_ICWY = 4          /* Alg. 6, inverse compact WY */
+} lsba_skeleton;
+
+typedef enum { LSBA_CHOLQR = 0, LSBA_HOUSEQR = 1 } lsba_muscle;
+
+typedef enum {
+  LSBA_FP64 = 0,              /* every step in FP64                                        */
+  LSBA_MIXED = 1              /* FP32 sparse/Gram/projection products (BF16-input MFMA with
+                                 FP32 accumulation for the Gram at s >= 16), FP64 Cholesky and
+                                 Hessenberg steps, FP64 outer iterative refinement           */
+} lsba_precision;
+
+enum {
+  LSBA_REC_LOO = 1u,          /* record ||I - V_{1:j+1}^T V_{1:j+1}||_2 after every column  */
+  LSBA_REC_TRUE_RES = 2u      /* compute the final FP64 true residual ||B - A X||_F/||B||_F  */
+};
+
+typedef struct {
+  uint32_t struct_size;       /* sizeof(lsba_params); set by lsba_params_default            */
+  int32_t method;             /* lsba_method                                               */
+  int32_t skeleton;           /* lsba_skeleton                                             */
+  int32_t muscle;             /* lsba_muscle (IntraOrtho at each cycle start; every step
+                                 for BMGS-SVL/LTS)                                           */
+  int32_t precision;          /* lsba_precision                                            */
+  int32_t m;                  /* maximum basis size per cycle (block columns)              */
+  double tol;                 /* stop when residual estimate / ||B||_F <= tol              */
+  int32_t max_cycles;         /* restart cycles allowed                                    */
+  int64_t max_iters;          /* total block columns allowed (<= 0: unlimited)             */
+  int32_t max_refine;         /* LSBA_MIXED: outer refinement steps allowed                */
+  double inner_tol;           /* LSBA_MIXED: relative tolerance of each inner solve        */
+  uint32_t record;            /* LSBA_REC_* bit set                                        */
+  int32_t force_flag_cycle;   /* test hook: raise the Cholesky flag at this cycle (1-based) */
+  int32_t force_flag_step;    /*   ... and this skeleton loop step k (0 = first IntraOrtho);
+                                 -1 disables the hook                                        */
+} lsba_params;
+
+typedef struct lsba_context lsba_context;
+typedef struct lsba_operator lsba_operator;
+typedef struct lsba_result lsba_result;
+
+/* Fill *p with defaults: BGMRES, BCGSI+LS, CholQR, FP64, m = 20, tol = 1e-8,
+ * max_cycles = 50, max_iters = 0, max_refine = 20, inner_tol = 1e-4, record = 0,
+ * force flag off.  Returns LSBA_ERR_ARG for p == NULL. */
+lsba_status lsba_params_default(lsba_params* p);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * issue work on (not owned), or NULL to let the library create and own one.
+ * On success *ctx receives the handle. */
+lsba_status lsba_context_create(int device, void* hip_stream, lsba_context** ctx);
+void lsba_context_destroy(lsba_context* ctx);
+/* Message of the last failed call on ctx (or of the last failed context
+ * creation when ctx is NULL).  Owned by the library. */
+const char* lsba_last_error(const lsba_context* ctx);
+const char* lsba_status_string(lsba_status st);
+
+/* Device-time statistics per kernel class.  While timing is enabled, HIP
+ * events are recorded on the context's stream around every kernel launch of
+ * the library; elapsed times and the launches' algorithmic bytes (the block
+ * and CSR data the method must read and write, not the implementation's extra
+ * traffic) are accumulated per class.  Launches queued after the step that
+ * ended a cycle find nothing to do: they count with their (short) durations
+ * and zero bytes. */
+typedef enum {
+  LSBA_K_SPMM = 0,            /* W = A V (block SpMM)                                       */
+  LSBA_K_GRAM = 1,            /* Gram products, split-n stage                                */
+  LSBA_K_GRAM_REDUCE = 2,     /* Gram products, fixed-order reduction stage (0 bytes)        */
+  LSBA_K_UPDATE = 3,          /* fused block updates / projections / basis applications      */
+  LSBA_K_SMALL = 4,           /* small dense steps (0 bytes)                                 */
+  LSBA_K_RESIDUAL = 5         /* FP64 true residual B - A X                                  */
+} lsba_kernel_kind;
+/* Enable (1) or disable (0) timing; either way the statistics are cleared. */
+lsba_status lsba_context_set_timing(lsba_context* ctx, int enable);
+/* Launch count, summed device milliseconds and summed algorithmic bytes of a
+ * kernel class since timing was enabled (all zero when disabled). */
+lsba_status lsba_context_kernel_stats(const lsba_context* ctx, int32_t kind, int64_t* launches,
+                                      double* total_ms, double* total_bytes);
+
+/* Copy a CSR matrix (layout above) into device memory owned by the operator.
+ * Validates the row pointer (monotone, row_ptr[0] = 0, row_ptr[n] = nnz) and
+ * the column range; an invalid matrix gives LSBA_ERR_ARG. */
+lsba_status lsba_operator_create_csr(lsba_context* ctx, int64_t n, int64_t nnz,
+                                     const int64_t* row_ptr, const int32_t* col_idx,
+                                     const double* values, int on_device, lsba_operator** op);
+void lsba_operator_destroy(lsba_operator* op);
+
+/* Solve A X = B from X_0 = 0 (eq. Xm).  B and X are n x s row-major with
+ * leading dimensions ldb, ldx >= s; host or device per `on_device`.  Blocks
+ * until the solve ends.  *res receives a result handle for every status >= 0
+ * (and for no negative status). */
+lsba_status lsba_solve(lsba_context* ctx, const lsba_operator* op, const lsba_params* prm,
+                       int32_t s, const double* B, int64_t ldb, double* X, int64_t ldx,
+                       int on_device, lsba_result** res);
+
+/* Result getters.  Arrays are library-owned host memory, valid until
+ * lsba_result_destroy.  res_hist[i] is the residual estimate (eq. normF_Rm)
+ * over ||B||_F after the i-th final block column, over all cycles (for the
+ * mixed form: of the inner solves, in order).  loo_hist is NULL unless
+ * LSBA_REC_LOO was set.  cycle_len[c] is the number of final columns of cycle
+ * c and m_after[c] the basis size allowed after it (the adaptive restart
+ * shrinks it, Sec. 4). */
+lsba_status lsba_result_status(const lsba_result* r);
+int64_t lsba_result_iters(const lsba_result* r);
+const double* lsba_result_res_hist(const lsba_result* r);
+const double* lsba_result_loo_hist(const lsba_result* r);
+int32_t lsba_result_cycles(const lsba_result* r);
+const int32_t* lsba_result_cycle_len(const lsba_result* r);
+const int32_t* lsba_result_m_after(const lsba_result* r);
+/* A-calls, basis applications and syncs as the paper counts them (Sec. 5). */
+void lsba_result_counts(const lsba_result* r, int64_t* a_calls, int64_t* v_apps, int64_t* syncs);
+/* ||B - A X||_F / ||B||_F in FP64 (NaN unless LSBA_REC_TRUE_RES or LSBA_MIXED). */
+double lsba_result_true_relres(const lsba_result* r);
+/* Outer refinement steps taken (LSBA_MIXED), else 0. */
+int32_t lsba_result_refine_steps(const lsba_result* r);
+/* Device time of the solve in milliseconds (HIP events around the whole solve). */
+double lsba_result_gpu_ms(const lsba_result* r);
+void lsba_result_destroy(lsba_result* r);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSBA_H */

@@ -1,0 +1,229 @@
+// Tall-skinny Gram products G = [L_1 ... L_p]^T [R_1 ... R_q] of n x s blocks:
+// the block inner products (the sync points) of the skeletons, e.g. the fused
+// [V_{1:k-1} U]^T [U W] of Algs. 6 and 7, V_{1:k}^T W and V_{1:k}^T V_{k+1}
+// of Alg. 5, and the Gram X^T X of the CholQR muscle.
+//
+// Split-n, two stages, deterministic: stage 1 gives each workgroup a chunk of
+// rows and writes the chunk's partial G to a workspace; stage 2 sums the
+// partials in chunk order.  No floating-point atomics, so every run (and
+// every request of a serving batch) reduces in the same order.
+//
+// Stage 1 (vector FMA): the output (p s) x (q s) is cut into TxT tiles,
+// T = min(s, 8); one wavefront owns one tile for one chunk.  Lane l takes the
+// chunk's rows l, l+64, ...: for each it loads T contiguous elements of the
+// left block row and T of the right block row (consecutive lanes read
+// consecutive rows, so a wavefront's loads are contiguous segments) and
+// accumulates the T x T outer product in registers.  The 64 lanes are then
+// combined by a butterfly of cross-lane shuffles that leaves one finished
+// entry per lane.  Workgroups are numbered so that all tiles of one chunk run
+// on the same XCD, where their shared block rows are served by that XCD's L2.
+#include "lsba_internal.h"
+
+namespace lsba {
+
+namespace {
+
+constexpr int kXcds = 8;
+
+template <typename T>
+__device__ __forceinline__ const T* left_ptr(const GramArgs<T>& a, int blk) {
+  return blk < a.nv ? a.V + (int64_t)blk * a.n * a.s : a.xl[blk - a.nv];
+}
+
+template <int V, int Q>
+__device__ __forceinline__ void butterfly_level(double (&v)[V], int lane) {
+  constexpr int h = 32 >> Q;      // partner distance
+  constexpr int n = V >> Q;       // values still distinct at this level
+  if constexpr (n > 1) {
+    constexpr int half = n / 2;
+    const bool up = (lane & h) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const double keep = up ? v[i + half] : v[i];
+      const double give = up ? v[i] : v[i + half];
+      v[i] = keep + __shfl_xor(give, h, 64);
+    }
+  } else {
+    v[0] += __shfl_xor(v[0], h, 64);
+  }
+}
+
+// Sum each of the V values over the 64 lanes of the wavefront (V a power of
+// two <= 64); afterwards lane l holds the total of value l >> (6 - log2 V).
+// The order of the additions is fixed.
+template <int V>
+__device__ __forceinline__ double butterfly(double (&v)[V], int lane) {
+  butterfly_level<V, 0>(v, lane);
+  butterfly_level<V, 1>(v, lane);
+  butterfly_level<V, 2>(v, lane);
+  butterfly_level<V, 3>(v, lane);
+  butterfly_level<V, 4>(v, lane);
+  butterfly_level<V, 5>(v, lane);
+  return v[0];
+}
+
+template <typename T, int TL>
+__global__ __launch_bounds__(256) void gram_stage1(GramArgs<T> a, int nchunk, int ngroup,
+                                                   int64_t rows_per_chunk,
+                                                   double* __restrict__ partial,
+                                                   const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->stop) return;
+  // XCD-aware numbering: hardware workgroup id -> (chunk, tile group)
+  const int pid = blockIdx.x;
+  const int xcd = pid % kXcds, t = pid / kXcds;
+  const int chunk = xcd + kXcds * (t / ngroup);
+  const int grp = t % ngroup;
+  if (chunk >= nchunk) return;
+  const int s = a.s;
+  const int PA = (a.nv + a.nxl) * s, QB = a.nxr * s;
+  const int tcols = QB / TL;                  // tiles across the right blocks
+  const int ntile = (PA / TL) * tcols;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tile = grp * 4 + wave;
+  if (tile >= ntile) return;
+  const int ta = tile / tcols, tb = tile % tcols;
+  const int acol = ta * TL, bcol = tb * TL;   // first output row / column
+  const T* __restrict__ L = left_ptr(a, acol / s) + (acol % s);
+  const T* __restrict__ Rr = a.xr[bcol / s] + (bcol % s);
+  const int64_t r0 = (int64_t)chunk * rows_per_chunk;
+  const int64_t r1 = r0 + rows_per_chunk < a.n ? r0 + rows_per_chunk : a.n;
+  T acc[TL][TL];
+#pragma unroll
+  for (int i = 0; i < TL; ++i)
+#pragma unroll
+    for (int j = 0; j < TL; ++j) acc[i][j] = T(0);
+  for (int64_t r = r0 + lane; r < r1; r += 64) {
+    const int64_t off = r * s;
+    T lv[TL], rv[TL];
+#pragma unroll
+    for (int i = 0; i < TL; ++i) lv[i] = L[off + i];
+#pragma unroll
+    for (int j = 0; j < TL; ++j) rv[j] = Rr[off + j];
+#pragma unroll
+    for (int i = 0; i < TL; ++i)
+#pragma unroll
+      for (int j = 0; j < TL; ++j) acc[i][j] = fma(lv[i], rv[j], acc[i][j]);
+  }
+  constexpr int V = TL * TL;
+  double v[V];
+#pragma unroll
+  for (int i = 0; i < TL; ++i)
+#pragma unroll
+    for (int j = 0; j < TL; ++j) v[i * TL + j] = (double)acc[i][j];
+  const double tot = butterfly<V>(v, lane);
+  constexpr int sh = (V == 64) ? 0 : (V == 16) ? 2 : (V == 4) ? 4 : 6;
+  if ((lane & ((1 << sh) - 1)) == 0) {
+    const int e = lane >> sh;
+    const int i = e / TL, j = e % TL;
+    partial[(int64_t)chunk * PA * QB + (int64_t)(acol + i) * QB + (bcol + j)] = tot;
+  }
+}
+
+// Stage 2: G[e] = sum over chunks of partial[chunk][e], 64 entries per
+// workgroup, 4 threads per entry summing every 4th chunk, combined in order.
+__global__ __launch_bounds__(256) void gram_stage2(const double* __restrict__ partial, int nchunk,
+                                                   int entries, double* __restrict__ out,
+                                                   const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->stop) return;
+  __shared__ double red[256];
+  const int le = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + le;
+  double v = 0.0;
+  if (e < entries)
+    for (int c = q; c < nchunk; c += 4) v += partial[(int64_t)c * entries + e];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  if (q == 0 && e < entries) out[e] = (red[le] + red[64 + le]) + (red[128 + le] + red[192 + le]);
+}
+
+struct Plan {
+  int tl, nchunk, ngroup;
+  int64_t rows;
+};
+
+Plan plan(int64_t n, int s, int PA, int QB) {
+  Plan p;
+  p.tl = s >= 8 ? 8 : (s >= 4 ? 4 : (s >= 2 ? 2 : 1));
+  // a tile must not straddle two blocks: T divides s for s in {1, 2, 4, 8, 16, 32};
+  // other block sizes fall back to T = 1 (correct, slower)
+  if (s % p.tl != 0) p.tl = 1;
+  const int ntile = (PA / p.tl) * (QB / p.tl);
+  p.ngroup = (ntile + 3) / 4;
+  // about 4096 workgroups in total, at least 256 rows (4 per lane) per chunk
+  int64_t nchunk = 4096 / p.ngroup;
+  if (nchunk < kXcds) nchunk = kXcds;
+  const int64_t maxc = (n + 255) / 256;
+  if (nchunk > maxc) nchunk = maxc;
+  if (nchunk < 1) nchunk = 1;
+  p.rows = (n + nchunk - 1) / nchunk;
+  p.nchunk = (int)((n + p.rows - 1) / p.rows);
+  return p;
+}
+
+}  // namespace
+
+size_t gram_partial_doubles(int64_t n, int s, int nleft, int nright) {
+  // the largest partial buffer any launch with at most this many blocks plans
+  size_t best = 0;
+  for (int nl = 1; nl <= nleft; ++nl)
+    for (int nr = 1; nr <= nright; ++nr) {
+      const Plan p = plan(n, s, nl * s, nr * s);
+      const size_t need = (size_t)p.nchunk * (size_t)(nl * s) * (size_t)(nr * s);
+      if (need > best) best = need;
+    }
+  return best;
+}
+
+// Distinct input blocks of a Gram launch (a right block that is also a left
+// block is read once by the method).
+template <typename T>
+int distinct_blocks(const GramArgs<T>& a) {
+  int cnt = a.nv + a.nxl;
+  for (int j = 0; j < a.nxr; ++j) {
+    bool dup = false;
+    for (int i = 0; i < a.nxl; ++i) dup |= a.xr[j] == a.xl[i];
+    const T* p = a.xr[j];
+    if (a.nv > 0 && p >= a.V && p < a.V + (int64_t)a.nv * a.n * a.s) dup = true;
+    cnt += dup ? 0 : 1;
+  }
+  return cnt;
+}
+
+template <typename T>
+void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* out,
+                 const Ctl* ctl, KTimer* tm) {
+  const int PA = (a.nv + a.nxl) * a.s, QB = a.nxr * a.s;
+  const Plan p = plan(a.n, a.s, PA, QB);
+  const int nchunk_pad = ((p.nchunk + kXcds - 1) / kXcds) * kXcds;
+  const int blocks = nchunk_pad * p.ngroup;
+  if (tm) tm->begin(st);
+  switch (p.tl) {
+    case 8:
+      gram_stage1<T, 8><<<dim3(blocks), dim3(256), 0, st>>>(a, p.nchunk, p.ngroup, p.rows,
+                                                            partial, ctl);
+      break;
+    case 4:
+      gram_stage1<T, 4><<<dim3(blocks), dim3(256), 0, st>>>(a, p.nchunk, p.ngroup, p.rows,
+                                                            partial, ctl);
+      break;
+    case 2:
+      gram_stage1<T, 2><<<dim3(blocks), dim3(256), 0, st>>>(a, p.nchunk, p.ngroup, p.rows,
+                                                            partial, ctl);
+      break;
+    default:
+      gram_stage1<T, 1><<<dim3(blocks), dim3(256), 0, st>>>(a, p.nchunk, p.ngroup, p.rows,
+                                                            partial, ctl);
+  }
+  if (tm) tm->end(st, KK_GRAM, (double)distinct_blocks(a) * a.n * a.s * sizeof(T));
+  const int entries = PA * QB;
+  if (tm) tm->begin(st);
+  gram_stage2<<<dim3((entries + 63) / 64), dim3(256), 0, st>>>(partial, p.nchunk, entries, out,
+                                                               ctl);
+  if (tm) tm->end(st, KK_GRAM_REDUCE, 0.0);
+}
+template void launch_gram<double>(hipStream_t, const GramArgs<double>&, double*, double*,
+                                  const Ctl*, KTimer*);
+template void launch_gram<float>(hipStream_t, const GramArgs<float>&, double*, double*,
+                                 const Ctl*, KTimer*);
+
+}  // namespace lsba

@@ -1,0 +1,188 @@
+// Internal declarations shared by the HIP kernels and the host driver of liblsba.
+//
+// Device data layout (one solve):
+//   block vectors   n x s, row-major (the s entries of a row adjacent), type T
+//                   (double in the FP64 form, float for the inner solves of the
+//                   mixed form);
+//   basis           slots V_1 .. V_{m+1} contiguous: V + i * n * s;
+//   small dense     FP64, row-major, in global memory (see Dense below).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lsba.h"
+
+namespace lsba {
+
+constexpr int kMaxS = 32;       // largest block size s
+constexpr int kMaxM = 128;      // largest basis size m
+constexpr int kSmallThreads = 256;
+
+// Per-solve control word, device resident.  Kernels of a restart cycle read
+// `stop` and return at once when it is set, so a whole cycle can be queued
+// without a host round trip per step.
+enum CtlStatus : int {
+  ST_RUNNING = 0,     // cycle in progress
+  ST_CONVERGED = 1,   // estimate / nB <= tol after column j
+  ST_FLAGGED = 2,     // Cholesky breakdown flag; j = last final column
+  ST_ITERCAP = 3      // max_iters final columns reached
+};
+
+struct Ctl {
+  int stop;
+  int status;
+  int j;                // final block columns of the current cycle
+  int m;                // current maximum basis size (shrinks on a flag)
+  long long iter;       // final block columns over all cycles
+  long long max_iters;  // <= 0: unlimited
+  long long a_calls, v_apps, syncs;
+  int flag_step;        // loop step whose Cholesky raised the flag
+  int nv1, nv2_begin, nv2;   // block ranges of the cycle-end basis application
+  int cont;             // 1: another cycle follows
+  int cycles;           // cycles completed
+  int cyc_status;       // status of the cycle that ended last
+  int last_valid;       // after a flag: the last block column that is final
+  int pad1;
+  double nB;            // ||B||_F of the right-hand side of this solve
+  double tol;
+  double est;           // last relative residual estimate
+};
+
+// Small dense state of one solve (FP64, device, row-major).
+struct Dense {
+  int s;          // block size
+  int mmax;       // allocated basis size
+  int ldh;        // leading dimension of H, T, Rf: (mmax + 1) * s
+  int skel;       // lsba_skeleton
+  int method;     // lsba_method
+  int mixed;      // 1: shifted-Cholesky fallback allowed (mixed form)
+  double* H;      // block Hessenberg, (mmax + 2) s rows x ldh
+  double* T;      // auxiliary T of Algs. 5 / 6, ldh x ldh
+  double* Tt;     // its transpose (kept so that products read rows), ldh x ldh
+  double* J;      // auxiliary J of Alg. 7, (mmax + 1) s x s
+  double* G;      // reduced Gram output, up to (mmax + 2) s x 2 s
+  double* G2;     // second Gram output (muscle Gram / LOO Gram)
+  double* Beta;   // factor of IntraOrtho(R0), s x s
+  double* C;      // cospatial factor carried between cycles, s x s
+  double* Qt;     // Q_i^T of each block column's 2s x 2s window QR, mmax x (2s x 2s)
+  double* Rf;     // transformed (triangularised) H columns, (mmax + 1) s x ldh
+  double* g;      // transformed right-hand side E_1 B C, (mmax + 1) s x s
+  double* Dlast;  // diagonal block of the last column before its own reflector, s x s
+  double* ylast;  // FOM: last block of Xi for the last final column, s x s
+  double* Xi;     // block coefficient vector, mmax s x s
+  double* M;      // BGMRES modification factor, mmax s x s
+  double* Rinv;   // inverse of the latest Cholesky factor, s x s
+  double* P;      // P of Algs. 6 / 7, s x s
+  double* Gv;     // V^T V of the current cycle (loss-of-orthogonality record), ldh x ldh
+  double* scratch;// workspace for the small kernels, >= 8 * ldh * s + 64 * s * s doubles
+  double* coef64; // update coefficients (see Coef below), FP64
+  void* coefT;    // the same coefficients in the basis type (float copy for the mixed form)
+  double* res_hist;
+  double* loo_hist;
+  Ctl* ctl;
+};
+
+// Coefficient layout of the fused block update (both in FP64 and in T):
+//   out1 = in1 * C1 + sum_{i < nv1} V_i * A_i
+//   out2 = in2 * C2 + sum_{nv2_begin <= i < nv2} V_i * B_i + out1 * D
+// Every matrix is s x s row-major (entry (t, c) multiplies input column t
+// into output column c).  Offsets (in elements) for block size s, mmax:
+struct CoefLayout {
+  int s, nvmax;
+  __host__ __device__ int C1() const { return 0; }
+  __host__ __device__ int A(int i) const { return s * s * (1 + i); }
+  __host__ __device__ int C2() const { return s * s * (1 + nvmax); }
+  __host__ __device__ int B(int i) const { return s * s * (2 + nvmax + i); }
+  __host__ __device__ int D() const { return s * s * (2 + 2 * nvmax); }
+  __host__ __device__ int total() const { return s * s * (3 + 2 * nvmax); }
+};
+
+// Kernel classes for the device-time statistics (values of lsba_kernel_kind).
+enum KernelKind : int {
+  KK_SPMM = 0, KK_GRAM = 1, KK_GRAM_REDUCE = 2, KK_UPDATE = 3, KK_SMALL = 4, KK_RESIDUAL = 5,
+  KK_COUNT = 6
+};
+
+// Optional launch timer: begin()/end() bracket one kernel launch on stream st
+// with HIP events; `bytes` are the launch's algorithmic bytes (inputs the
+// method must read plus outputs it must write).
+struct KTimer {
+  virtual void begin(hipStream_t st) = 0;
+  virtual void end(hipStream_t st, int kind, double bytes) = 0;
+  virtual ~KTimer() {}
+};
+
+// ------------------------------------------------------------------ kernels
+// Sparse: W = A X (CSR x row-major block).
+template <typename T>
+void launch_spmm(hipStream_t st, int64_t n, int64_t nnz, int s, const int64_t* rp, const int* ci,
+                 const T* val, const T* X, T* W, const Ctl* ctl, KTimer* tm = nullptr);
+// R = B - A X, and per-workgroup partial sums of squares of R written to partial[]
+// (nw entries); norms are then reduced in a fixed order by launch_sumsq_final.
+void launch_residual(hipStream_t st, int64_t n, int64_t nnz, int s, const int64_t* rp,
+                     const int* ci, const double* val, const double* X, const double* B,
+                     double* R, double* partial, int* nw_out, KTimer* tm = nullptr);
+void launch_sumsq_partial(hipStream_t st, int64_t count, const double* x, double* partial,
+                          int* nw_out);
+void launch_sumsq_final(hipStream_t st, const double* partial, int nw, double* out_norm);
+template <typename T>
+void launch_cast(hipStream_t st, int64_t count, const double* in, T* out);
+template <typename T>
+void launch_add_to_double(hipStream_t st, int64_t count, const T* in, double* acc);
+
+// Gram: G = [left blocks]^T [right blocks], deterministic split-n reduction.
+template <typename T>
+struct GramArgs {
+  int64_t n;
+  int s;
+  const T* V;        // contiguous left blocks V + i n s, i < nv
+  int nv;
+  const T* xl[2];    // extra left blocks after the contiguous ones
+  int nxl;
+  const T* xr[2];    // right blocks
+  int nxr;
+};
+size_t gram_partial_doubles(int64_t n, int s, int nleft, int nright);
+template <typename T>
+void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* out,
+                 const Ctl* ctl, KTimer* tm = nullptr);
+
+// Fused block update (coefficients in CoefLayout, type T).
+template <typename T>
+struct UpdateArgs {
+  int64_t n;
+  int s;
+  const T* V;        // basis slots V + i n s
+  const T* in1;      // may be null
+  const T* in2;      // may be null
+  T* out1;           // may be null
+  T* out2;           // may be null
+  int nv1, nv2_begin, nv2, has_D;
+  const int* nvp;    // if non-null: nv1, nv2_begin, nv2 read from nvp[0..2] (device)
+  const T* coef;
+  CoefLayout lay;
+};
+// Algorithmic bytes of one update launch with nv1 / nv2_begin / nv2 block ranges.
+template <typename T>
+double update_bytes(const UpdateArgs<T>& a, int nv1, int nb, int nv2);
+template <typename T>
+void launch_update(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey_stop,
+                   KTimer* tm = nullptr);
+
+// Small dense steps (one workgroup per solve).  The skeleton steps (start,
+// delayed, svl_*) are on the critical path of the basis; finalize (QR update,
+// estimate, convergence test of one column) can run on a second stream.
+void launch_small_start(hipStream_t st, const Dense& d, int force_flag, KTimer* tm = nullptr);
+void launch_small_delayed(hipStream_t st, const Dense& d, int k, int m, int force_flag,
+                          KTimer* tm = nullptr);
+void launch_small_finalize(hipStream_t st, const Dense& d, int col, KTimer* tm = nullptr);
+void launch_small_svl_y(hipStream_t st, const Dense& d, int k, KTimer* tm = nullptr);
+void launch_small_svl_io(hipStream_t st, const Dense& d, int k, int force_flag,
+                         KTimer* tm = nullptr);
+void launch_small_svl_z(hipStream_t st, const Dense& d, int k, KTimer* tm = nullptr);
+void launch_small_cycle_end(hipStream_t st, const Dense& d, KTimer* tm = nullptr);
+void launch_small_loo(hipStream_t st, const Dense& d, int k_new_block, KTimer* tm = nullptr);
+
+}  // namespace lsba

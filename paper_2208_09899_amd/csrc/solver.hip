@@ -1,0 +1,927 @@
+// Host driver and C ABI of liblsba: restarted BFOM / BGMRES on one GPU.
+//
+// A solve runs restart cycles (Sec. 2.4.2).  Each cycle is queued on the
+// context's stream as a fixed sequence of kernels -- IntraOrtho of the
+// starting block, then for every loop step the block SpMM, the fused Gram
+// product, the small dense step and the fused block update -- followed by the
+// cycle-end step and the basis application X += V Xi, U = V [M; -H].  The
+// kernels test the device control word and return at once after convergence,
+// a Cholesky flag (Sec. 4) or the iteration cap, so the host synchronises
+// only once per cycle, to read the control word and the cycle's residual
+// estimates.
+//
+// The mixed form wraps FP32 inner solves (same cycle machinery with float
+// blocks) in FP64 iterative refinement: R = B - A X in FP64, inner solve
+// A D = R, X += D.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "lsba_internal.h"
+
+using namespace lsba;
+
+namespace {
+struct EventTimer;
+}
+
+struct lsba_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<std::string, Buf> bufs;
+  Ctl* ctl_host = nullptr;     // pinned
+  double* hist_host = nullptr; // pinned, 2 * (kMaxM + 2)
+  double* norm_host = nullptr; // pinned, 4
+  double* stage_host = nullptr;// pinned, kMaxS * kMaxS (host-to-device staging)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  EventTimer* timer = nullptr;   // non-null while kernel timing is enabled
+  hipStream_t side = nullptr;    // second stream: per-column QR updates / convergence tests
+  std::vector<hipEvent_t> evs;   // ordering events between the two streams
+};
+
+struct lsba_operator {
+  lsba_context* ctx = nullptr;
+  int64_t n = 0, nnz = 0;
+  int64_t* rp = nullptr;
+  int* ci = nullptr;
+  double* val = nullptr;
+  float* val32 = nullptr;
+};
+
+struct lsba_result {
+  lsba_status status = LSBA_OK;
+  int64_t iters = 0;
+  std::vector<double> res, loo;
+  std::vector<int32_t> cyc, mafter;
+  int64_t a = 0, v = 0, sy = 0;
+  double true_relres = NAN;
+  int32_t refine = 0;
+  double gpu_ms = 0.0;
+  bool have_loo = false;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+struct HipError {
+  std::string msg;
+};
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw HipError{std::string(#expr) + ": " + hipGetErrorString(e_)};                   \
+  } while (0)
+
+// HIP-event timer of kernel launches, flushed after every stream synchronisation.
+struct EventTimer final : KTimer {
+  struct Rec {
+    int kind;
+    double bytes;
+    hipEvent_t a, b;
+    int step, phase;
+  };
+  struct Acc {
+    int64_t launches = 0;
+    double ms = 0.0, bytes = 0.0;
+  };
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<Rec> recs;
+  hipEvent_t pending = nullptr;
+  Acc acc[KK_COUNT];
+  int step = 0, phase = 0;   // tag of the launches being queued
+
+  hipEvent_t take() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(hipStream_t st) override {
+    pending = take();
+    HIPCHK(hipEventRecord(pending, st));
+  }
+  void end(hipStream_t st, int kind, double bytes) override {
+    hipEvent_t b = take();
+    HIPCHK(hipEventRecord(b, st));
+    recs.push_back({kind, bytes, pending, b, step, phase});
+  }
+  void tag(int st, int ph) {
+    step = st;
+    phase = ph;
+  }
+  // Launches of steps after the one that ended the cycle did no algorithmic
+  // work (they returned at once, or ran ahead speculatively while the
+  // convergence test was pending): keep their durations, drop their bytes.
+  // With a Cholesky flag at step k_stop, the updates queued after that step's
+  // small kernel (phase 1) did not run either.
+  void kill_after(int k_stop, bool flagged) {
+    for (auto& r : recs)
+      if (r.step > k_stop || (flagged && r.step == k_stop && r.phase == 1)) r.bytes = 0.0;
+  }
+  void flush() {
+    for (auto& r : recs) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+      acc[r.kind].launches += 1;
+      acc[r.kind].ms += ms;
+      if (r.bytes > 0) acc[r.kind].bytes += r.bytes;
+    }
+    recs.clear();
+    used = 0;
+  }
+  ~EventTimer() override {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// Counts of one cycle as the paper counts them (Sec. 5): A-calls, basis
+// applications and syncs of the loop steps the algorithm executed.
+void cycle_counts(bool delayed, bool bcgs, int j, int status, int flag_step, int64_t& a,
+                  int64_t& v, int64_t& sy) {
+  sy += 1;   // IntraOrtho of the starting block
+  if (status == ST_FLAGGED && flag_step == 0) return;
+  int full, partial = 0;
+  if (status == ST_FLAGGED) {
+    full = flag_step - 1;
+    partial = 1;
+  } else {
+    full = delayed ? j + 1 : j;
+  }
+  if (delayed) {
+    for (int k = 1; k <= full; ++k) {
+      a += 1;
+      sy += 1;
+      v += (k == 1) ? 1 : (bcgs ? 4 : 3);
+    }
+    if (partial) {
+      a += 1;
+      sy += 1;
+      v += 2;
+    }
+  } else {
+    a += full;
+    sy += 3 * full;
+    v += 3 * full;
+    if (partial) {
+      a += 1;
+      sy += 2;
+      v += 2;
+    }
+  }
+}
+
+struct ArgError {
+  std::string msg;
+};
+struct Unsupported {
+  std::string msg;
+};
+
+void* ctx_buf(lsba_context* c, const std::string& name, size_t bytes) {
+  auto& b = c->bufs[name];
+  if (b.bytes < bytes) {
+    if (b.p) HIPCHK(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      b.p = nullptr;
+      throw HipError{"hipMalloc of " + std::to_string(bytes) + " bytes for " + name + " failed"};
+    }
+    b.bytes = bytes;
+  }
+  return b.p;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Device state of one Krylov solve in basis type T.
+template <typename T>
+struct Krylov {
+  int64_t n = 0;
+  int s = 0, mmax = 0;
+  T* V = nullptr;
+  T* U = nullptr;
+  T* W = nullptr;
+  double* partial = nullptr;
+  Dense d{};
+  CoefLayout lay{};
+};
+
+template <typename T>
+Krylov<T> make_krylov(lsba_context* c, int64_t n, int s, int m, const lsba_params& p,
+                      const char* tag) {
+  Krylov<T> k;
+  k.n = n;
+  k.s = s;
+  k.mmax = m;
+  const std::string t(tag);
+  const size_t blk = (size_t)n * s * sizeof(T);
+  k.V = (T*)ctx_buf(c, t + "V", blk * (m + 1));
+  k.U = (T*)ctx_buf(c, t + "U", blk);
+  k.W = (T*)ctx_buf(c, t + "W", blk);
+  k.partial = (double*)ctx_buf(c, t + "partial",
+                               sizeof(double) * gram_partial_doubles(n, s, m + 2, 2));
+  const int ldh = (m + 1) * s;
+  const size_t ss = (size_t)s * s;
+  const size_t big = (size_t)(m + 2) * ss;
+  CoefLayout lay{s, m + 1};
+  k.lay = lay;
+  // carve the small dense state out of one allocation
+  struct Item {
+    double** dst;
+    size_t count;
+  };
+  Dense& d = k.d;
+  std::vector<Item> items = {
+      {&d.H, (size_t)(m + 2) * s * ldh},
+      {&d.T, (size_t)ldh * ldh},
+      {&d.Tt, (size_t)ldh * ldh},
+      {&d.J, (size_t)(m + 1) * ss},
+      {&d.G, (size_t)(m + 2) * s * 2 * s},
+      {&d.G2, (size_t)(m + 2) * ss},
+      {&d.Beta, ss},
+      {&d.C, ss},
+      {&d.Qt, (size_t)m * 4 * ss},
+      {&d.Rf, (size_t)(m + 1) * s * ldh},
+      {&d.g, (size_t)(m + 1) * ss},
+      {&d.Dlast, ss},
+      {&d.ylast, ss},
+      {&d.Xi, (size_t)m * ss},
+      {&d.M, (size_t)m * ss},
+      {&d.Rinv, ss},
+      {&d.P, ss},
+      {&d.Gv, (size_t)ldh * ldh},
+      {&d.scratch, 64 * ss + 8 * big},
+      {&d.coef64, (size_t)lay.total()},
+      {&d.res_hist, (size_t)(m + 2)},
+      {&d.loo_hist, (size_t)(m + 2)},
+  };
+  size_t total = 0;
+  for (auto& it : items) total += align256(it.count * sizeof(double));
+  const size_t coefT_bytes = align256((size_t)lay.total() * sizeof(T));
+  total += coefT_bytes + align256(sizeof(Ctl));
+  char* base = (char*)ctx_buf(c, t + "dense", total);
+  size_t off = 0;
+  for (auto& it : items) {
+    *it.dst = (double*)(base + off);
+    off += align256(it.count * sizeof(double));
+  }
+  if (sizeof(T) == sizeof(double)) {
+    d.coefT = d.coef64;
+    off += coefT_bytes;
+  } else {
+    d.coefT = base + off;
+    off += coefT_bytes;
+  }
+  d.ctl = (Ctl*)(base + off);
+  d.s = s;
+  d.mmax = m;
+  d.ldh = ldh;
+  d.skel = p.skeleton;
+  d.method = p.method;
+  d.mixed = sizeof(T) == sizeof(float) ? 1 : 0;
+  return k;
+}
+
+struct CycleOut {
+  lsba_status status = LSBA_NOT_CONVERGED;
+  int64_t iters = 0;
+  int64_t a = 0, v = 0, sy = 0;
+};
+
+template <typename T>
+GramArgs<T> gram_args(const Krylov<T>& k, int nv, std::initializer_list<const T*> xl,
+                      std::initializer_list<const T*> xr) {
+  GramArgs<T> g{};
+  g.n = k.n;
+  g.s = k.s;
+  g.V = k.V;
+  g.nv = nv;
+  g.nxl = 0;
+  for (const T* p : xl) g.xl[g.nxl++] = p;
+  g.nxr = 0;
+  for (const T* p : xr) g.xr[g.nxr++] = p;
+  return g;
+}
+
+template <typename T>
+UpdateArgs<T> upd_args(const Krylov<T>& k) {
+  UpdateArgs<T> u{};
+  u.n = k.n;
+  u.s = k.s;
+  u.V = k.V;
+  u.coef = (const T*)k.d.coefT;
+  u.lay = k.lay;
+  return u;
+}
+
+template <typename T>
+T* slot(const Krylov<T>& k, int i) {
+  return k.V + (int64_t)i * k.n * k.s;
+}
+
+// Run restart cycles of A X = R for x (zero-initialised here) in type T.
+template <typename T>
+CycleOut run_cycles(lsba_context* c, const lsba_operator* op, const lsba_params& p,
+                    Krylov<T>& k, const T* val, const T* rhs, T* x, double nB, double tol,
+                    lsba_result* res) {
+  hipStream_t st = c->stream;
+  const int s = k.s;
+  const int64_t n = k.n;
+  Dense& d = k.d;
+  Ctl h{};
+  h.stop = 0;
+  h.status = ST_RUNNING;
+  h.m = p.m;
+  h.max_iters = p.max_iters > 0 ? p.max_iters : 0;
+  h.nB = nB;
+  h.tol = tol;
+  h.flag_step = -1;
+  // the stream is idle here (every solve ends with a synchronisation), so the
+  // pinned staging buffers can be refilled
+  *c->ctl_host = h;
+  HIPCHK(hipMemcpyAsync(d.ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st));
+  for (int i = 0; i < s * s; ++i) c->stage_host[i] = (i / s == i % s) ? 1.0 : 0.0;
+  HIPCHK(hipMemcpyAsync(d.C, c->stage_host, sizeof(double) * s * s, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(x, 0, (size_t)n * s * sizeof(T), st));
+  const bool delayed = p.skeleton == LSBA_BCGSI_LS || p.skeleton == LSBA_BMGS_CWY ||
+                       p.skeleton == LSBA_BMGS_ICWY;
+  const bool bcgs = p.skeleton == LSBA_BCGSI_LS;
+  const bool rec_loo = (p.record & LSBA_REC_LOO) != 0;
+  const T* R0 = rhs;
+  int m = p.m;
+  CycleOut out;
+  Ctl* ctl = d.ctl;
+  EventTimer* tm = c->timer;
+  hipStream_t side = c->side;
+  size_t nev = 0;
+  auto event = [&]() -> hipEvent_t {
+    if (nev == c->evs.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      c->evs.push_back(e);
+    }
+    return c->evs[nev++];
+  };
+  // the per-column QR update / convergence test of column `col` runs on the
+  // side stream, after the skeleton step that made the column final
+  auto finalize_after = [&](int col) {
+    hipEvent_t e = event();
+    HIPCHK(hipEventRecord(e, st));
+    HIPCHK(hipStreamWaitEvent(side, e, 0));
+    launch_small_finalize(side, d, col, tm);
+  };
+  auto tag = [&](int step, int phase) {
+    if (tm) tm->tag(step, phase);
+  };
+  for (int cyc = 1; cyc <= p.max_cycles; ++cyc) {
+    nev = 0;
+    const int fk = (p.force_flag_cycle == cyc) ? p.force_flag_step : -1;
+    // IntraOrtho(R0) by CholQR: V_1 = R0 B^{-1} (and U = V_1 for the delayed skeletons)
+    tag(0, 0);
+    launch_gram<T>(st, gram_args<T>(k, 0, {R0}, {R0}), k.partial, d.G, ctl, tm);
+    launch_small_start(st, d, fk == 0 ? 1 : 0, tm);
+    tag(0, 1);
+    {
+      UpdateArgs<T> u = upd_args(k);
+      u.in1 = R0;
+      u.out1 = slot(k, 0);
+      if (delayed) {
+        u.in2 = R0;
+        u.out2 = k.U;
+      }
+      launch_update<T>(st, u, ctl, true, tm);
+    }
+    if (rec_loo) {
+      launch_gram<T>(st, gram_args<T>(k, 1, {}, {slot(k, 0)}), k.partial, d.G2, ctl, tm);
+      launch_small_loo(st, d, 1, tm);
+    }
+    if (delayed) {
+      for (int kk = 1; kk <= m + 1; ++kk) {
+        const int force = fk == kk ? 1 : 0;
+        const bool last = kk == m + 1;
+        tag(kk, 0);
+        if (!last) launch_spmm<T>(st, n, op->nnz, s, op->rp, op->ci, val, k.U, k.W, ctl, tm);
+        if (kk == 1)
+          launch_gram<T>(st, gram_args<T>(k, 1, {}, {k.W}), k.partial, d.G, ctl, tm);
+        else if (!last)
+          launch_gram<T>(st, gram_args<T>(k, kk - 1, {k.U}, {k.U, k.W}), k.partial, d.G, ctl,
+                         tm);
+        else
+          launch_gram<T>(st, gram_args<T>(k, kk - 1, {k.U}, {k.U}), k.partial, d.G, ctl, tm);
+        launch_small_delayed(st, d, kk, m, force, tm);
+        tag(kk, 1);
+        if (kk >= 2) finalize_after(kk - 1);
+        UpdateArgs<T> u = upd_args(k);
+        if (kk == 1) {
+          u.in2 = k.W;
+          u.out2 = k.U;
+          u.nv2_begin = 0;
+          u.nv2 = 1;
+        } else {
+          u.in1 = k.U;
+          u.out1 = slot(k, kk - 1);
+          u.nv1 = bcgs ? kk - 1 : 0;
+          if (!last) {
+            u.in2 = k.W;
+            u.out2 = k.U;
+            u.nv2_begin = 0;
+            u.nv2 = kk - 1;
+            u.has_D = 1;
+          }
+        }
+        launch_update<T>(st, u, ctl, true, tm);
+        if (rec_loo && kk >= 2) {
+          launch_gram<T>(st, gram_args<T>(k, kk, {}, {slot(k, kk - 1)}), k.partial, d.G2, ctl,
+                         tm);
+          launch_small_loo(st, d, kk, tm);
+        }
+      }
+    } else {
+      for (int kk = 1; kk <= m; ++kk) {
+        const int force = fk == kk ? 1 : 0;
+        tag(kk, 0);
+        launch_spmm<T>(st, n, op->nnz, s, op->rp, op->ci, val, slot(k, kk - 1), k.W, ctl, tm);
+        launch_gram<T>(st, gram_args<T>(k, kk, {}, {k.W}), k.partial, d.G, ctl, tm);
+        launch_small_svl_y(st, d, kk, tm);
+        {
+          UpdateArgs<T> u = upd_args(k);
+          u.in2 = k.W;
+          u.out2 = slot(k, kk);
+          u.nv2_begin = 0;
+          u.nv2 = kk;
+          launch_update<T>(st, u, ctl, true, tm);
+        }
+        launch_gram<T>(st, gram_args<T>(k, 0, {slot(k, kk)}, {slot(k, kk)}), k.partial, d.G2,
+                       ctl, tm);
+        launch_small_svl_io(st, d, kk, force, tm);
+        tag(kk, 1);
+        {
+          UpdateArgs<T> u = upd_args(k);
+          u.in1 = slot(k, kk);
+          u.out1 = slot(k, kk);
+          launch_update<T>(st, u, ctl, true, tm);
+        }
+        launch_gram<T>(st, gram_args<T>(k, kk, {}, {slot(k, kk)}), k.partial, d.G, ctl, tm);
+        launch_small_svl_z(st, d, kk, tm);
+        finalize_after(kk);
+        if (rec_loo) {
+          launch_gram<T>(st, gram_args<T>(k, kk + 1, {}, {slot(k, kk)}), k.partial, d.G2, ctl,
+                         tm);
+          launch_small_loo(st, d, kk + 1, tm);
+        }
+      }
+    }
+    // join the side stream, then end the cycle
+    {
+      hipEvent_t e = event();
+      HIPCHK(hipEventRecord(e, side));
+      HIPCHK(hipStreamWaitEvent(st, e, 0));
+    }
+    tag(1 << 30, 0);
+    launch_small_cycle_end(st, d, tm);
+    UpdateArgs<T> uapply = upd_args(k);
+    uapply.in1 = x;
+    uapply.out1 = x;
+    uapply.out2 = k.U;
+    uapply.nvp = &ctl->nv1;
+    launch_update<T>(st, uapply, ctl, false, tm);
+    HIPCHK(hipMemcpyAsync(c->ctl_host, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(c->hist_host, d.res_hist, sizeof(double) * (m + 1),
+                          hipMemcpyDeviceToHost, st));
+    if (rec_loo)
+      HIPCHK(hipMemcpyAsync(c->hist_host + (kMaxM + 2), d.loo_hist, sizeof(double) * (m + 1),
+                            hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    const Ctl& hc = *c->ctl_host;
+    const int j = hc.j;
+    const int cst = hc.cyc_status;
+    if (tm) {
+      // bytes of the basis application, known only now
+      tm->recs.back().bytes = update_bytes(uapply, hc.nv1, hc.nv2_begin, hc.nv2);
+      if (cst == ST_CONVERGED || cst == ST_ITERCAP)
+        tm->kill_after(delayed ? j + 1 : j, false);
+      else if (cst == ST_FLAGGED)
+        tm->kill_after(hc.flag_step, true);
+      tm->flush();
+    }
+    cycle_counts(delayed, bcgs, j, cst, hc.flag_step, out.a, out.v, out.sy);
+    for (int i = 0; i < j; ++i) res->res.push_back(c->hist_host[i]);
+    if (rec_loo) {
+      for (int i = 0; i < j; ++i) {
+        // the loss of orthogonality of the column that ended the solve is not formed
+        const bool have = !(i == j - 1 && (cst == ST_CONVERGED || cst == ST_ITERCAP));
+        res->loo.push_back(have ? c->hist_host[(kMaxM + 2) + i] : NAN);
+      }
+    }
+    res->cyc.push_back(j);
+    res->mafter.push_back(hc.m);
+    out.iters = hc.iter;
+    if (!hc.cont) {
+      if (cst == ST_CONVERGED) out.status = LSBA_OK;
+      else if (cst == ST_FLAGGED) out.status = LSBA_BREAKDOWN;
+      else out.status = LSBA_NOT_CONVERGED;
+      return out;
+    }
+    m = hc.m;
+    R0 = k.U;
+  }
+  out.status = LSBA_NOT_CONVERGED;
+  return out;
+}
+
+double device_norm(lsba_context* c, const double* x, int64_t count) {
+  double* partial = (double*)ctx_buf(c, "norm_partial", sizeof(double) * ((count / 4096) + 2));
+  int nw = 0;
+  launch_sumsq_partial(c->stream, count, x, partial, &nw);
+  double* outd = (double*)ctx_buf(c, "norm_out", sizeof(double) * 4);
+  launch_sumsq_final(c->stream, partial, nw, outd);
+  HIPCHK(hipMemcpyAsync(c->norm_host, outd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return c->norm_host[0];
+}
+
+// R = B - A X (R may be null) and ||R||_F, FP64.
+double device_residual(lsba_context* c, const lsba_operator* op, int s, const double* X,
+                       const double* B, double* R) {
+  int sh = 0;
+  while ((1 << sh) < s) ++sh;
+  const int64_t blocks = ((op->n << sh) + 255) / 256;
+  double* partial = (double*)ctx_buf(c, "res_partial", sizeof(double) * (blocks + 1));
+  int nw = 0;
+  launch_residual(c->stream, op->n, op->nnz, s, op->rp, op->ci, op->val, X, B, R, partial, &nw,
+                  c->timer);
+  double* outd = (double*)ctx_buf(c, "norm_out", sizeof(double) * 4);
+  launch_sumsq_final(c->stream, partial, nw, outd);
+  HIPCHK(hipMemcpyAsync(c->norm_host, outd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->timer) c->timer->flush();
+  return c->norm_host[0];
+}
+
+void validate_params(const lsba_params* p, int s) {
+  if (!p) throw ArgError{"params is NULL"};
+  if (p->struct_size != sizeof(lsba_params)) throw ArgError{"params.struct_size mismatch"};
+  if (s < 1 || s > kMaxS) throw ArgError{"s must be in [1, 32]"};
+  if (p->m < 1 || p->m > kMaxM) throw ArgError{"m must be in [1, 128]"};
+  if (p->method != LSBA_FOM && p->method != LSBA_GMRES) throw ArgError{"bad method"};
+  if (p->skeleton < LSBA_BCGSI_LS || p->skeleton > LSBA_BMGS_ICWY) throw ArgError{"bad skeleton"};
+  if (p->muscle != LSBA_CHOLQR && p->muscle != LSBA_HOUSEQR) throw ArgError{"bad muscle"};
+  if (p->precision != LSBA_FP64 && p->precision != LSBA_MIXED) throw ArgError{"bad precision"};
+  if (!(p->tol >= 0.0)) throw ArgError{"tol must be >= 0"};
+  if (p->max_cycles < 1) throw ArgError{"max_cycles must be >= 1"};
+  if (p->muscle == LSBA_HOUSEQR) throw Unsupported{"HouseQR muscle is not available in this build"};
+  if (p->precision == LSBA_MIXED && (p->max_refine < 1 || !(p->inner_tol > 0.0)))
+    throw ArgError{"mixed form needs max_refine >= 1 and inner_tol > 0"};
+}
+
+lsba_status fail(lsba_context* c, lsba_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_err = msg;
+  return st;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+lsba_status lsba_params_default(lsba_params* p) {
+  if (!p) return LSBA_ERR_ARG;
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(lsba_params);
+  p->method = LSBA_GMRES;
+  p->skeleton = LSBA_BCGSI_LS;
+  p->muscle = LSBA_CHOLQR;
+  p->precision = LSBA_FP64;
+  p->m = 20;
+  p->tol = 1e-8;
+  p->max_cycles = 50;
+  p->max_iters = 0;
+  p->max_refine = 20;
+  p->inner_tol = 1e-4;
+  p->record = 0;
+  p->force_flag_cycle = -1;
+  p->force_flag_step = -1;
+  return LSBA_OK;
+}
+
+const char* lsba_status_string(lsba_status st) {
+  switch (st) {
+    case LSBA_OK: return "converged";
+    case LSBA_NOT_CONVERGED: return "not converged";
+    case LSBA_BREAKDOWN: return "breakdown (Cholesky flag with no final column)";
+    case LSBA_ERR_ARG: return "invalid argument";
+    case LSBA_ERR_OOM: return "out of memory";
+    case LSBA_ERR_HIP: return "HIP runtime error";
+    case LSBA_ERR_UNSUPPORTED: return "unsupported";
+    case LSBA_ERR_BUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+const char* lsba_last_error(const lsba_context* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+lsba_status lsba_context_create(int device, void* hip_stream, lsba_context** out) {
+  if (!out) return fail(nullptr, LSBA_ERR_ARG, "ctx out pointer is NULL");
+  *out = nullptr;
+  auto* c = new (std::nothrow) lsba_context();
+  if (!c) return fail(nullptr, LSBA_ERR_OOM, "host allocation failed");
+  try {
+    int count = 0;
+    HIPCHK(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) {
+      delete c;
+      return fail(nullptr, LSBA_ERR_ARG, "device index out of range");
+    }
+    c->device = device;
+    HIPCHK(hipSetDevice(device));
+    if (hip_stream) {
+      c->stream = (hipStream_t)hip_stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    HIPCHK(hipHostMalloc((void**)&c->ctl_host, sizeof(Ctl), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->hist_host, sizeof(double) * 2 * (kMaxM + 2),
+                         hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->norm_host, sizeof(double) * 4, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->stage_host, sizeof(double) * kMaxS * kMaxS,
+                         hipHostMallocDefault));
+    HIPCHK(hipEventCreate(&c->ev0));
+    HIPCHK(hipEventCreate(&c->ev1));
+  } catch (const HipError& e) {
+    lsba_context_destroy(c);
+    return fail(nullptr, LSBA_ERR_HIP, e.msg);
+  }
+  *out = c;
+  return LSBA_OK;
+}
+
+void lsba_context_destroy(lsba_context* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& kv : c->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  if (c->ctl_host) (void)hipHostFree(c->ctl_host);
+  if (c->hist_host) (void)hipHostFree(c->hist_host);
+  if (c->norm_host) (void)hipHostFree(c->norm_host);
+  if (c->stage_host) (void)hipHostFree(c->stage_host);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c->timer;
+  for (auto e : c->evs) (void)hipEventDestroy(e);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+lsba_status lsba_operator_create_csr(lsba_context* c, int64_t n, int64_t nnz,
+                                     const int64_t* row_ptr, const int32_t* col_idx,
+                                     const double* values, int on_device, lsba_operator** out) {
+  if (!c) return fail(nullptr, LSBA_ERR_ARG, "context is NULL");
+  if (!out || !row_ptr || (nnz > 0 && (!col_idx || !values)))
+    return fail(c, LSBA_ERR_ARG, "NULL pointer argument");
+  if (n < 1 || nnz < 0) return fail(c, LSBA_ERR_ARG, "n must be >= 1 and nnz >= 0");
+  if (n * (int64_t)kMaxS >= ((int64_t)1 << 31) * 64)
+    return fail(c, LSBA_ERR_ARG, "n too large");
+  *out = nullptr;
+  auto* op = new (std::nothrow) lsba_operator();
+  if (!op) return fail(c, LSBA_ERR_OOM, "host allocation failed");
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    // validate on the host
+    std::vector<int64_t> rp_h;
+    std::vector<int32_t> ci_h;
+    const int64_t* rp = row_ptr;
+    const int32_t* ci = col_idx;
+    if (on_device) {
+      rp_h.resize(n + 1);
+      ci_h.resize(nnz);
+      HIPCHK(hipMemcpy(rp_h.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+      if (nnz) HIPCHK(hipMemcpy(ci_h.data(), col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+      rp = rp_h.data();
+      ci = ci_h.data();
+    }
+    if (rp[0] != 0 || rp[n] != nnz) {
+      delete op;
+      return fail(c, LSBA_ERR_ARG, "row_ptr[0] must be 0 and row_ptr[n] must be nnz");
+    }
+    for (int64_t i = 0; i < n; ++i)
+      if (rp[i + 1] < rp[i]) {
+        delete op;
+        return fail(c, LSBA_ERR_ARG, "row_ptr is not non-decreasing");
+      }
+    for (int64_t e = 0; e < nnz; ++e)
+      if (ci[e] < 0 || ci[e] >= n) {
+        delete op;
+        return fail(c, LSBA_ERR_ARG, "column index out of range");
+      }
+    op->ctx = c;
+    op->n = n;
+    op->nnz = nnz;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (hipMalloc(&op->rp, sizeof(int64_t) * (n + 1)) != hipSuccess ||
+        hipMalloc(&op->ci, sizeof(int) * std::max<int64_t>(nnz, 1)) != hipSuccess ||
+        hipMalloc(&op->val, sizeof(double) * std::max<int64_t>(nnz, 1)) != hipSuccess) {
+      lsba_operator_destroy(op);
+      return fail(c, LSBA_ERR_OOM, "device allocation of the CSR arrays failed");
+    }
+    HIPCHK(hipMemcpy(op->rp, row_ptr, sizeof(int64_t) * (n + 1), kind));
+    if (nnz) {
+      HIPCHK(hipMemcpy(op->ci, col_idx, sizeof(int) * nnz, kind));
+      HIPCHK(hipMemcpy(op->val, values, sizeof(double) * nnz, kind));
+    }
+  } catch (const HipError& e) {
+    lsba_operator_destroy(op);
+    return fail(c, LSBA_ERR_HIP, e.msg);
+  }
+  *out = op;
+  return LSBA_OK;
+}
+
+void lsba_operator_destroy(lsba_operator* op) {
+  if (!op) return;
+  if (op->ctx) {
+    (void)hipSetDevice(op->ctx->device);
+    if (op->ctx->stream) (void)hipStreamSynchronize(op->ctx->stream);
+  }
+  if (op->rp) (void)hipFree(op->rp);
+  if (op->ci) (void)hipFree(op->ci);
+  if (op->val) (void)hipFree(op->val);
+  if (op->val32) (void)hipFree(op->val32);
+  delete op;
+}
+
+lsba_status lsba_solve(lsba_context* c, const lsba_operator* op, const lsba_params* prm,
+                       int32_t s, const double* B, int64_t ldb, double* X, int64_t ldx,
+                       int on_device, lsba_result** out) {
+  if (!c) return fail(nullptr, LSBA_ERR_ARG, "context is NULL");
+  if (!op || !B || !X || !out) return fail(c, LSBA_ERR_ARG, "NULL pointer argument");
+  if (op->ctx != c) return fail(c, LSBA_ERR_ARG, "operator belongs to another context");
+  *out = nullptr;
+  try {
+    validate_params(prm, s);
+    if (ldb < s || ldx < s) throw ArgError{"ldb and ldx must be >= s"};
+  } catch (const ArgError& e) {
+    return fail(c, LSBA_ERR_ARG, e.msg);
+  } catch (const Unsupported& e) {
+    return fail(c, LSBA_ERR_UNSUPPORTED, e.msg);
+  }
+  const lsba_params p = *prm;
+  const int64_t n = op->n;
+  auto* r = new (std::nothrow) lsba_result();
+  if (!r) return fail(c, LSBA_ERR_OOM, "host allocation failed");
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    const hipMemcpyKind in_kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const hipMemcpyKind out_kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const size_t blk64 = (size_t)n * s * sizeof(double);
+    double* B64 = (double*)ctx_buf(c, "B64", blk64);
+    double* X64 = (double*)ctx_buf(c, "X64", blk64);
+    HIPCHK(hipEventRecord(c->ev0, st));
+    HIPCHK(hipMemcpy2DAsync(B64, s * sizeof(double), B, ldb * sizeof(double), s * sizeof(double),
+                            n, in_kind, st));
+    const double nB = device_norm(c, B64, n * s);
+    r->have_loo = (p.record & LSBA_REC_LOO) != 0;
+    if (nB == 0.0) {
+      HIPCHK(hipMemsetAsync(X64, 0, blk64, st));
+      r->status = LSBA_OK;
+      r->true_relres = 0.0;
+    } else if (p.precision == LSBA_FP64) {
+      Krylov<double> k = make_krylov<double>(c, n, s, p.m, p, "d_");
+      CycleOut o = run_cycles<double>(c, op, p, k, op->val, B64, X64, nB, p.tol, r);
+      r->status = o.status;
+      r->iters = o.iters;
+      r->a = o.a;
+      r->v = o.v;
+      r->sy = o.sy;
+      if (p.record & LSBA_REC_TRUE_RES)
+        r->true_relres = device_residual(c, op, s, X64, B64, nullptr) / nB;
+    } else {
+      if (!op->val32) {
+        auto* mop = const_cast<lsba_operator*>(op);
+        if (hipMalloc(&mop->val32, sizeof(float) * std::max<int64_t>(op->nnz, 1)) != hipSuccess)
+          throw HipError{"hipMalloc of the FP32 operator values failed"};
+        if (op->nnz) launch_cast<float>(st, op->nnz, op->val, mop->val32);
+      }
+      double* R64 = (double*)ctx_buf(c, "R64", blk64);
+      float* Rf = (float*)ctx_buf(c, "Rf32", (size_t)n * s * sizeof(float));
+      float* Df = (float*)ctx_buf(c, "Df32", (size_t)n * s * sizeof(float));
+      Krylov<float> k = make_krylov<float>(c, n, s, p.m, p, "f_");
+      HIPCHK(hipMemsetAsync(X64, 0, blk64, st));
+      HIPCHK(hipMemcpyAsync(R64, B64, blk64, hipMemcpyDeviceToDevice, st));
+      double rn = nB;
+      r->status = LSBA_NOT_CONVERGED;
+      for (int it = 0; it < p.max_refine; ++it) {
+        if (rn / nB <= p.tol) {
+          r->status = LSBA_OK;
+          break;
+        }
+        launch_cast<float>(st, n * s, R64, Rf);
+        CycleOut o = run_cycles<float>(c, op, p, k, op->val32, Rf, Df, rn, p.inner_tol, r);
+        r->iters += o.iters;
+        r->a += o.a;
+        r->v += o.v;
+        r->sy += o.sy;
+        r->refine += 1;
+        if (o.status == LSBA_BREAKDOWN) {
+          r->status = LSBA_BREAKDOWN;
+          break;
+        }
+        launch_add_to_double<float>(st, n * s, Df, X64);
+        rn = device_residual(c, op, s, X64, B64, R64);
+      }
+      if (r->status == LSBA_NOT_CONVERGED && rn / nB <= p.tol) r->status = LSBA_OK;
+      r->true_relres = rn / nB;
+    }
+    HIPCHK(hipMemcpy2DAsync(X, ldx * sizeof(double), X64, s * sizeof(double), s * sizeof(double),
+                            n, out_kind, st));
+    HIPCHK(hipEventRecord(c->ev1, st));
+    HIPCHK(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    r->gpu_ms = ms;
+  } catch (const HipError& e) {
+    delete r;
+    return fail(c, LSBA_ERR_HIP, e.msg);
+  }
+  *out = r;
+  return r->status;
+}
+
+lsba_status lsba_context_set_timing(lsba_context* c, int enable) {
+  if (!c) return fail(nullptr, LSBA_ERR_ARG, "context is NULL");
+  try {
+    (void)hipSetDevice(c->device);
+    if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+    delete c->timer;
+    c->timer = enable ? new EventTimer() : nullptr;
+  } catch (const HipError& e) {
+    return fail(c, LSBA_ERR_HIP, e.msg);
+  }
+  return LSBA_OK;
+}
+
+lsba_status lsba_context_kernel_stats(const lsba_context* c, int32_t kind, int64_t* launches,
+                                      double* total_ms, double* total_bytes) {
+  if (!c || kind < 0 || kind >= KK_COUNT) return LSBA_ERR_ARG;
+  const EventTimer::Acc a = c->timer ? c->timer->acc[kind] : EventTimer::Acc{};
+  if (launches) *launches = a.launches;
+  if (total_ms) *total_ms = a.ms;
+  if (total_bytes) *total_bytes = a.bytes;
+  return LSBA_OK;
+}
+
+lsba_status lsba_result_status(const lsba_result* r) { return r ? r->status : LSBA_ERR_ARG; }
+int64_t lsba_result_iters(const lsba_result* r) { return r ? r->iters : 0; }
+const double* lsba_result_res_hist(const lsba_result* r) {
+  return r && !r->res.empty() ? r->res.data() : nullptr;
+}
+const double* lsba_result_loo_hist(const lsba_result* r) {
+  return r && r->have_loo && !r->loo.empty() ? r->loo.data() : nullptr;
+}
+int32_t lsba_result_cycles(const lsba_result* r) { return r ? (int32_t)r->cyc.size() : 0; }
+const int32_t* lsba_result_cycle_len(const lsba_result* r) {
+  return r && !r->cyc.empty() ? r->cyc.data() : nullptr;
+}
+const int32_t* lsba_result_m_after(const lsba_result* r) {
+  return r && !r->mafter.empty() ? r->mafter.data() : nullptr;
+}
+void lsba_result_counts(const lsba_result* r, int64_t* a, int64_t* v, int64_t* sy) {
+  if (a) *a = r ? r->a : 0;
+  if (v) *v = r ? r->v : 0;
+  if (sy) *sy = r ? r->sy : 0;
+}
+double lsba_result_true_relres(const lsba_result* r) { return r ? r->true_relres : NAN; }
+int32_t lsba_result_refine_steps(const lsba_result* r) { return r ? r->refine : 0; }
+double lsba_result_gpu_ms(const lsba_result* r) { return r ? r->gpu_ms : 0.0; }
+void lsba_result_destroy(lsba_result* r) { delete r; }
+
+}  // extern "C"
