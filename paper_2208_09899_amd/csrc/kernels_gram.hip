@@ -149,11 +149,14 @@ Plan plan(int64_t n, int s, int PA, int QB) {
   if (s % p.tl != 0) p.tl = 1;
   const int ntile = (PA / p.tl) * (QB / p.tl);
   p.ngroup = (ntile + 3) / 4;
-  // about 4096 workgroups in total, at least 256 rows (4 per lane) per chunk
-  int64_t nchunk = 4096 / p.ngroup;
-  if (nchunk < kXcds) nchunk = kXcds;
-  const int64_t maxc = (n + 255) / 256;
-  if (nchunk > maxc) nchunk = maxc;
+  // Rows per lane: 16 by default (enough work per wavefront to amortise the
+  // cross-lane reduction), fewer (down to 4) while the grid has under 1024
+  // workgroups, more when the partial buffer would pass 8192 partial tiles.
+  int64_t rpl = 16;
+  auto chunks = [&](int64_t r) { return (n + 64 * r - 1) / (64 * r); };
+  while (rpl > 4 && chunks(rpl) * p.ngroup < 1024) rpl >>= 1;
+  while (chunks(rpl) * p.ngroup > 8192 && chunks(rpl) > kXcds) rpl <<= 1;
+  int64_t nchunk = chunks(rpl);
   if (nchunk < 1) nchunk = 1;
   p.rows = (n + nchunk - 1) / nchunk;
   p.nchunk = (int)((n + p.rows - 1) / p.rows);

@@ -148,28 +148,6 @@ __device__ bool chol_up(const double* Om, int ldo, double* R, int s, double shif
     R[e] = (j >= i) ? Om[(int64_t)i * ldo + j] + (i == j ? shift : 0.0) : 0.0;
   }
   bar();
-  if (s <= 8) {
-    // a few hundred flops: one thread, no barriers
-    if (threadIdx.x == 0) {
-      int ok = 1;
-      for (int j = 0; j < s && ok; ++j) {
-        double dd = R[j * s + j];
-        for (int i = 0; i < j; ++i) dd -= R[i * s + j] * R[i * s + j];
-        ok = (dd > 0.0) && isfinite(dd);
-        if (!ok) break;
-        const double rjj = sqrt(dd);
-        R[j * s + j] = rjj;
-        for (int l = j + 1; l < s; ++l) {
-          double v = R[j * s + l];
-          for (int i = 0; i < j; ++i) v -= R[i * s + j] * R[i * s + l];
-          R[j * s + l] = v / rjj;
-        }
-      }
-      okf = ok;
-    }
-    bar();
-    return okf != 0;
-  }
   for (int j = 0; j < s; ++j) {
     if (threadIdx.x == 0) {
       double dd = R[j * s + j];

@@ -41,12 +41,10 @@ __device__ __forceinline__ void axpy_mat(const T (&x)[S], const T* __restrict__ 
   }
 }
 
-template <typename T, int S, bool EXACT>
+template <typename T, int S, bool EXACT, bool LDSCOEF>
 __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<T> a, const Ctl* __restrict__ ctl,
                                                      int obey_stop) {
   if (obey_stop && ctl && ctl->stop) return;
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= a.n) return;
   int nv1 = a.nv1, nb = a.nv2_begin, nv2 = a.nv2;
   if (a.nvp) {
     nv1 = a.nvp[0];
@@ -55,9 +53,24 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<T> a, const Ctl*
     if (nv1 < 0) return;
   }
   const int s = EXACT ? S : a.s;
+  const T* __restrict__ C = a.coef;
+  if constexpr (LDSCOEF) {
+    // stage the coefficients used by this launch in LDS once per workgroup;
+    // every thread then reads them as broadcasts
+    // (same layout as in memory; the A blocks are copied only when used)
+    extern __shared__ char smem_raw[];
+    T* cl = reinterpret_cast<T*>(smem_raw);
+    const int ss = s * s;
+    const int a_end = a.lay.A(nv1 > 0 ? nv1 : 0);
+    for (int e = threadIdx.x; e < a_end; e += blockDim.x) cl[e] = C[e];
+    for (int e = a.lay.C2() + threadIdx.x; e < a.lay.D() + ss; e += blockDim.x) cl[e] = C[e];
+    __syncthreads();
+    C = cl;
+  }
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= a.n) return;
   const int64_t off = row * s;
   const int64_t bstride = a.n * s;
-  const T* __restrict__ C = a.coef;
   T o1[S], o2[S], x[S];
 #pragma unroll
   for (int c = 0; c < S; ++c) {
@@ -96,10 +109,25 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<T> a, const Ctl*
 template <typename T, int S>
 void launch_s(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey) {
   const int64_t blocks = (a.n + 255) / 256;
-  if (a.s == S)
-    update_kernel<T, S, true><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a, ctl, obey ? 1 : 0);
-  else
-    update_kernel<T, S, false><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(a, ctl, obey ? 1 : 0);
+  // coefficients in LDS for s <= 8 (at most (3 + 2 (m+1)) s^2 elements, 34 KiB
+  // for s = 8, m = 30); larger s reads them through the scalar cache
+  const size_t coef_bytes = (size_t)a.lay.total() * sizeof(T);
+  const bool lds = S <= 8 && coef_bytes <= 64 * 1024;
+  if (a.s == S) {
+    if (lds)
+      update_kernel<T, S, true, true><<<dim3((unsigned)blocks), dim3(256), coef_bytes, st>>>(
+          a, ctl, obey ? 1 : 0);
+    else
+      update_kernel<T, S, true, false><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(
+          a, ctl, obey ? 1 : 0);
+  } else {
+    if (lds)
+      update_kernel<T, S, false, true><<<dim3((unsigned)blocks), dim3(256), coef_bytes, st>>>(
+          a, ctl, obey ? 1 : 0);
+    else
+      update_kernel<T, S, false, false><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(
+          a, ctl, obey ? 1 : 0);
+  }
 }
 
 }  // namespace
