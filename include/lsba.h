@@ -127,8 +127,8 @@ const char* lsba_last_error(const lsba_context* ctx);
 const char* lsba_status_string(lsba_status st);
 
 /* Device-time statistics per kernel class.  While timing is enabled, HIP
- * events are recorded on the context's stream around every kernel launch of
- * the library; elapsed times and the launches' algorithmic bytes (the block
+ * events are recorded on the launching stream around every kernel launch of
+ * the selected classes; elapsed times and the launches' algorithmic bytes (the block
  * and CSR data the method must read and write, not the implementation's extra
  * traffic) are accumulated per class.  Launches queued after the step that
  * ended a cycle find nothing to do: they count with their (short) durations
@@ -141,8 +141,12 @@ typedef enum {
   LSBA_K_SMALL = 4,           /* small dense steps (0 bytes)                                 */
   LSBA_K_RESIDUAL = 5         /* FP64 true residual B - A X                                  */
 } lsba_kernel_kind;
-/* Enable (1) or disable (0) timing; either way the statistics are cleared. */
-lsba_status lsba_context_set_timing(lsba_context* ctx, int enable);
+/* Time the kernel classes whose bits (1u << lsba_kernel_kind) are set in
+ * kind_mask (LSBA_TIME_ALL: every class; 0: timing off).  Launches of other
+ * classes are not bracketed by events, so timing one class perturbs the run
+ * least.  Either way the statistics are cleared. */
+#define LSBA_TIME_ALL 0x3Fu
+lsba_status lsba_context_set_timing(lsba_context* ctx, uint32_t kind_mask);
 /* Launch count, summed device milliseconds and summed algorithmic bytes of a
  * kernel class since timing was enabled (all zero when disabled). */
 lsba_status lsba_context_kernel_stats(const lsba_context* ctx, int32_t kind, int64_t* launches,

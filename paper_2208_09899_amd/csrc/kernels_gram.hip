@@ -92,17 +92,33 @@ __global__ __launch_bounds__(256) void gram_stage1(GramArgs<T> a, int nchunk, in
   for (int i = 0; i < TL; ++i)
 #pragma unroll
     for (int j = 0; j < TL; ++j) acc[i][j] = T(0);
-  for (int64_t r = r0 + lane; r < r1; r += 64) {
-    const int64_t off = r * s;
-    T lv[TL], rv[TL];
+  // rows r0 + lane + 64 q; the rows of the next NB - 1 iterations are in
+  // flight while one is multiplied (NB register buffers indexed at compile time)
+  constexpr int NB = TL >= 8 ? 2 : 3;
+  const int64_t nq = r1 > r0 + lane ? (r1 - (r0 + lane) + 63) / 64 : 0;
+  T lv[NB][TL], rv[NB][TL];
+  auto load = [&](int64_t q, int b) {
+    const int64_t off = (r0 + lane + 64 * q) * s;
 #pragma unroll
-    for (int i = 0; i < TL; ++i) lv[i] = L[off + i];
+    for (int i = 0; i < TL; ++i) lv[b][i] = L[off + i];
 #pragma unroll
-    for (int j = 0; j < TL; ++j) rv[j] = Rr[off + j];
+    for (int j = 0; j < TL; ++j) rv[b][j] = Rr[off + j];
+  };
 #pragma unroll
-    for (int i = 0; i < TL; ++i)
+  for (int b = 0; b < NB; ++b)
+    if (b < nq) load(b, b);
+  for (int64_t q0 = 0; q0 < nq; q0 += NB) {
 #pragma unroll
-      for (int j = 0; j < TL; ++j) acc[i][j] = fma(lv[i], rv[j], acc[i][j]);
+    for (int b = 0; b < NB; ++b) {
+      const int64_t q = q0 + b;
+      if (q < nq) {
+#pragma unroll
+        for (int i = 0; i < TL; ++i)
+#pragma unroll
+          for (int j = 0; j < TL; ++j) acc[i][j] = fma(lv[b][i], rv[b][j], acc[i][j]);
+        if (q + NB < nq) load(q + NB, b);
+      }
+    }
   }
   constexpr int V = TL * TL;
   double v[V];
@@ -119,21 +135,40 @@ __global__ __launch_bounds__(256) void gram_stage1(GramArgs<T> a, int nchunk, in
   }
 }
 
-// Stage 2: G[e] = sum over chunks of partial[chunk][e], 64 entries per
-// workgroup, 4 threads per entry summing every 4th chunk, combined in order.
+// Stage 2: G[e] = sum over chunks of partial[chunk][e].  A workgroup takes
+// 2^ew_log2 consecutive entries and 256 >> ew_log2 groups of threads; group q
+// sums chunks q, q + groups, ... (several loads in flight), and the groups'
+// sums are added in group order, so the result does not depend on timing.
 __global__ __launch_bounds__(256) void gram_stage2(const double* __restrict__ partial, int nchunk,
-                                                   int entries, double* __restrict__ out,
+                                                   int entries, int ew_log2,
+                                                   double* __restrict__ out,
                                                    const Ctl* __restrict__ ctl) {
   if (ctl && ctl->stop) return;
   __shared__ double red[256];
-  const int le = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int e = blockIdx.x * 64 + le;
+  const int ew = 1 << ew_log2, groups = 256 >> ew_log2;
+  const int le = threadIdx.x & (ew - 1), q = threadIdx.x >> ew_log2;
+  const int e = blockIdx.x * ew + le;
   double v = 0.0;
-  if (e < entries)
-    for (int c = q; c < nchunk; c += 4) v += partial[(int64_t)c * entries + e];
+  if (e < entries) {
+    const double* p = partial + e;
+    int c = q;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (; c + 3 * groups < nchunk; c += 4 * groups) {
+      a0 += p[(int64_t)c * entries];
+      a1 += p[(int64_t)(c + groups) * entries];
+      a2 += p[(int64_t)(c + 2 * groups) * entries];
+      a3 += p[(int64_t)(c + 3 * groups) * entries];
+    }
+    for (; c < nchunk; c += groups) a0 += p[(int64_t)c * entries];
+    v = (a0 + a1) + (a2 + a3);
+  }
   red[threadIdx.x] = v;
   __syncthreads();
-  if (q == 0 && e < entries) out[e] = (red[le] + red[64 + le]) + (red[128 + le] + red[192 + le]);
+  if (q == 0 && e < entries) {
+    double t = 0.0;
+    for (int g = 0; g < groups; ++g) t += red[g * ew + le];
+    out[e] = t;
+  }
 }
 
 struct Plan {
@@ -199,7 +234,7 @@ void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* 
   const Plan p = plan(a.n, a.s, PA, QB);
   const int nchunk_pad = ((p.nchunk + kXcds - 1) / kXcds) * kXcds;
   const int blocks = nchunk_pad * p.ngroup;
-  if (tm) tm->begin(st);
+  if (tm) tm->begin(st, KK_GRAM);
   switch (p.tl) {
     case 8:
       gram_stage1<T, 8><<<dim3(blocks), dim3(256), 0, st>>>(a, p.nchunk, p.ngroup, p.rows,
@@ -219,9 +254,12 @@ void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* 
   }
   if (tm) tm->end(st, KK_GRAM, (double)distinct_blocks(a) * a.n * a.s * sizeof(T));
   const int entries = PA * QB;
-  if (tm) tm->begin(st);
-  gram_stage2<<<dim3((entries + 63) / 64), dim3(256), 0, st>>>(partial, p.nchunk, entries, out,
-                                                               ctl);
+  // entries per workgroup: 8 .. 64, aiming at >= 256 workgroups
+  int ewl = 3;
+  while (ewl < 6 && ((entries + (1 << ewl) - 1) >> ewl) > 256) ++ewl;
+  if (tm) tm->begin(st, KK_GRAM_REDUCE);
+  gram_stage2<<<dim3((entries + (1 << ewl) - 1) >> ewl), dim3(256), 0, st>>>(
+      partial, p.nchunk, entries, ewl, out, ctl);
   if (tm) tm->end(st, KK_GRAM_REDUCE, 0.0);
 }
 template void launch_gram<double>(hipStream_t, const GramArgs<double>&, double*, double*,

@@ -116,7 +116,7 @@ void launch_spmm(hipStream_t st, int64_t n, int64_t nnz, int s, const int64_t* r
   const int sh = lanes_shift(s);
   const int64_t threads = n << sh;
   const int64_t blocks = (threads + 255) / 256;
-  if (tm) tm->begin(st);
+  if (tm) tm->begin(st, KK_SPMM);
   spmm_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(n, s, sh, rp, ci, val, X, W, ctl);
   if (tm)
     tm->end(st, KK_SPMM,
@@ -133,7 +133,7 @@ void launch_residual(hipStream_t st, int64_t n, int64_t nnz, int s, const int64_
   const int sh = lanes_shift(s);
   const int64_t threads = n << sh;
   const int64_t blocks = (threads + 255) / 256;
-  if (tm) tm->begin(st);
+  if (tm) tm->begin(st, KK_RESIDUAL);
   residual_kernel<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(n, s, sh, rp, ci, val, X, B, R,
                                                                  partial);
   if (tm)

@@ -41,6 +41,55 @@ __device__ __forceinline__ void axpy_mat(const T (&x)[S], const T* __restrict__ 
   }
 }
 
+// The inputs of one launch in order: in1 (if any), the basis blocks
+// i0 .. i0 + nbas - 1, in2 (if any).
+template <typename T>
+struct InputSeq {
+  const T* in1;
+  const T* in2;
+  const T* V;
+  int64_t off, bstride;
+  int h1, nbas, i0, nv1, nb, nv2;
+  __device__ __forceinline__ const T* ptr(int q) const {
+    if (q < h1) return in1 + off;
+    q -= h1;
+    if (q < nbas) return V + (int64_t)(i0 + q) * bstride + off;
+    return in2 + off;
+  }
+};
+
+// Apply input q (its row in x) to the output rows.
+template <typename T, int S>
+__device__ __forceinline__ void apply_input(const InputSeq<T>& in, int q, const T (&x)[S],
+                                            const T* __restrict__ C, const CoefLayout& lay,
+                                            int s, T (&o1)[S], T (&o2)[S]) {
+  // coefficient blocks for o1 / o2 (null: input does not feed that output)
+  const T* c1 = nullptr;
+  const T* c2 = nullptr;
+  if (q < in.h1) {
+    c1 = C + lay.C1();
+  } else if (q - in.h1 < in.nbas) {
+    const int i = in.i0 + q - in.h1;
+    if (i < in.nv1) c1 = C + lay.A(i);
+    if (i >= in.nb && i < in.nv2) c2 = C + lay.B(i);
+  } else {
+    c2 = C + lay.C2();
+  }
+  if (c1) axpy_mat<T, S>(x, c1, s, o1);
+  if (c2) axpy_mat<T, S>(x, c2, s, o2);
+}
+
+// Use input q, then start loading input q + NB into the same registers.
+template <typename T, int S, int NB>
+__device__ __forceinline__ void pipe_step(const InputSeq<T>& in, int nin, int q, T (&x)[S],
+                                          const T* __restrict__ C, const CoefLayout& lay,
+                                          int s, T (&o1)[S], T (&o2)[S]) {
+  if (q < nin) {
+    apply_input<T, S>(in, q, x, C, lay, s, o1, o2);
+    if (q + NB < nin) load_row<T, S>(in.ptr(q + NB), s, x);
+  }
+}
+
 template <typename T, int S, bool EXACT, bool LDSCOEF>
 __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<T> a, const Ctl* __restrict__ ctl,
                                                      int obey_stop) {
@@ -71,27 +120,39 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<T> a, const Ctl*
   if (row >= a.n) return;
   const int64_t off = row * s;
   const int64_t bstride = a.n * s;
-  T o1[S], o2[S], x[S];
+  T o1[S], o2[S];
 #pragma unroll
   for (int c = 0; c < S; ++c) {
     o1[c] = T(0);
     o2[c] = T(0);
   }
-  if (a.in1) {
-    load_row<T, S>(a.in1 + off, s, x);
-    axpy_mat<T, S>(x, C + a.lay.C1(), s, o1);
-  }
+  // The rows of the next NB - 1 inputs are in flight while one is being
+  // applied (NB register buffers, named so that every index is static).
   const int nvmax = nv1 > nv2 ? nv1 : nv2;
-  const int i0 = nv1 > 0 ? 0 : nb;
-  for (int i = i0; i < nvmax; ++i) {
-    const bool u1 = i < nv1, u2 = (i >= nb) && (i < nv2);
-    load_row<T, S>(a.V + (int64_t)i * bstride + off, s, x);
-    if (u1) axpy_mat<T, S>(x, C + a.lay.A(i), s, o1);
-    if (u2) axpy_mat<T, S>(x, C + a.lay.B(i), s, o2);
-  }
-  if (a.in2) {
-    load_row<T, S>(a.in2 + off, s, x);
-    axpy_mat<T, S>(x, C + a.lay.C2(), s, o2);
+  InputSeq<T> in;
+  in.in1 = a.in1;
+  in.in2 = a.in2;
+  in.V = a.V;
+  in.off = off;
+  in.bstride = bstride;
+  in.h1 = a.in1 ? 1 : 0;
+  in.i0 = nv1 > 0 ? 0 : nb;
+  in.nbas = nvmax > in.i0 ? nvmax - in.i0 : 0;
+  in.nv1 = nv1;
+  in.nb = nb;
+  in.nv2 = nv2;
+  const int nin = in.h1 + in.nbas + (a.in2 ? 1 : 0);
+  constexpr int NB = S <= 8 ? 3 : (S <= 16 ? 2 : 1);
+  T x0[S], x1[S], x2[S];
+  if (nin > 0) load_row<T, S>(in.ptr(0), s, x0);
+  if constexpr (NB > 1)
+    if (nin > 1) load_row<T, S>(in.ptr(1), s, x1);
+  if constexpr (NB > 2)
+    if (nin > 2) load_row<T, S>(in.ptr(2), s, x2);
+  for (int q0 = 0; q0 < nin; q0 += NB) {
+    pipe_step<T, S, NB>(in, nin, q0, x0, C, a.lay, s, o1, o2);
+    if constexpr (NB > 1) pipe_step<T, S, NB>(in, nin, q0 + 1, x1, C, a.lay, s, o1, o2);
+    if constexpr (NB > 2) pipe_step<T, S, NB>(in, nin, q0 + 2, x2, C, a.lay, s, o1, o2);
   }
   if (a.has_D) axpy_mat<T, S>(o1, C + a.lay.D(), s, o2);
   if (a.out1) {
@@ -149,7 +210,7 @@ template double update_bytes<float>(const UpdateArgs<float>&, int, int, int);
 template <typename T>
 void launch_update(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey_stop,
                    KTimer* tm) {
-  if (tm) tm->begin(st);
+  if (tm) tm->begin(st, KK_UPDATE);
   if (a.s <= 1) launch_s<T, 1>(st, a, ctl, obey_stop);
   else if (a.s <= 2) launch_s<T, 2>(st, a, ctl, obey_stop);
   else if (a.s <= 4) launch_s<T, 4>(st, a, ctl, obey_stop);

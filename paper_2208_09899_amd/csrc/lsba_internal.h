@@ -62,7 +62,9 @@ struct Dense {
   double* T;      // auxiliary T of Algs. 5 / 6, ldh x ldh
   double* Tt;     // its transpose (kept so that products read rows), ldh x ldh
   double* J;      // auxiliary J of Alg. 7, (mmax + 1) s x s
-  double* G;      // reduced Gram output, up to (mmax + 2) s x 2 s
+  double* G;      // reduced Gram output of loop step k at G + k * gstride, up to (k s) x 2 s
+  long long gstride;   // 0: one slot (Alg. 5); delayed skeletons keep one slot per step so
+                       // that the off-path H / J / QR work may lag the basis kernels
   double* G2;     // second Gram output (muscle Gram / LOO Gram)
   double* Beta;   // factor of IntraOrtho(R0), s x s
   double* C;      // cospatial factor carried between cycles, s x s
@@ -75,6 +77,8 @@ struct Dense {
   double* M;      // BGMRES modification factor, mmax s x s
   double* Rinv;   // inverse of the latest Cholesky factor, s x s
   double* P;      // P of Algs. 6 / 7, s x s
+  double* RiS;    // Alg. 7: R^{-1} of loop step k at RiS + k s^2
+  double* PS;     // Alg. 7: P of loop step k at PS + k s^2
   double* Gv;     // V^T V of the current cycle (loss-of-orthogonality record), ldh x ldh
   double* scratch;// workspace for the small kernels, >= 8 * ldh * s + 64 * s * s doubles
   double* coef64; // update coefficients (see Coef below), FP64
@@ -105,11 +109,12 @@ enum KernelKind : int {
   KK_COUNT = 6
 };
 
-// Optional launch timer: begin()/end() bracket one kernel launch on stream st
-// with HIP events; `bytes` are the launch's algorithmic bytes (inputs the
+// Optional launch timer: begin()/end() bracket one kernel launch of class
+// `kind` on stream st with HIP events (classes outside the timer's mask are
+// not bracketed); `bytes` are the launch's algorithmic bytes (inputs the
 // method must read plus outputs it must write).
 struct KTimer {
-  virtual void begin(hipStream_t st) = 0;
+  virtual void begin(hipStream_t st, int kind) = 0;
   virtual void end(hipStream_t st, int kind, double bytes) = 0;
   virtual ~KTimer() {}
 };
@@ -178,6 +183,9 @@ void launch_small_start(hipStream_t st, const Dense& d, int force_flag, KTimer* 
 void launch_small_delayed(hipStream_t st, const Dense& d, int k, int m, int force_flag,
                           KTimer* tm = nullptr);
 void launch_small_finalize(hipStream_t st, const Dense& d, int col, KTimer* tm = nullptr);
+// Alg. 7 off the basis path, after loop step k >= 2: H_{1:k-1,k-1} = J + Y, the
+// J recurrence, then the QR update / estimate / convergence test of column k-1.
+void launch_small_side(hipStream_t st, const Dense& d, int k, int m, KTimer* tm = nullptr);
 void launch_small_svl_y(hipStream_t st, const Dense& d, int k, KTimer* tm = nullptr);
 void launch_small_svl_io(hipStream_t st, const Dense& d, int k, int force_flag,
                          KTimer* tm = nullptr);

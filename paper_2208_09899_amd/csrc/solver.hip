@@ -103,6 +103,9 @@ struct EventTimer final : KTimer {
   hipEvent_t pending = nullptr;
   Acc acc[KK_COUNT];
   int step = 0, phase = 0;   // tag of the launches being queued
+  uint32_t mask;             // bit k: time launches of class k
+  explicit EventTimer(uint32_t m) : mask(m) {}
+  bool on(int kind) const { return (mask >> kind) & 1u; }
 
   hipEvent_t take() {
     if (used == pool.size()) {
@@ -112,11 +115,13 @@ struct EventTimer final : KTimer {
     }
     return pool[used++];
   }
-  void begin(hipStream_t st) override {
+  void begin(hipStream_t st, int kind) override {
+    if (!on(kind)) return;
     pending = take();
     HIPCHK(hipEventRecord(pending, st));
   }
   void end(hipStream_t st, int kind, double bytes) override {
+    if (!on(kind)) return;
     hipEvent_t b = take();
     HIPCHK(hipEventRecord(b, st));
     recs.push_back({kind, bytes, pending, b, step, phase});
@@ -242,6 +247,10 @@ Krylov<T> make_krylov(lsba_context* c, int64_t n, int s, int m, const lsba_param
   const size_t big = (size_t)(m + 2) * ss;
   CoefLayout lay{s, m + 1};
   k.lay = lay;
+  // the delayed skeletons keep each loop step's Gram output in its own slot
+  const bool per_step = p.skeleton == LSBA_BCGSI_LS || p.skeleton == LSBA_BMGS_CWY ||
+                        p.skeleton == LSBA_BMGS_ICWY;
+  const size_t gslot = (size_t)(m + 1) * s * 2 * s;
   // carve the small dense state out of one allocation
   struct Item {
     double** dst;
@@ -253,7 +262,7 @@ Krylov<T> make_krylov(lsba_context* c, int64_t n, int s, int m, const lsba_param
       {&d.T, (size_t)ldh * ldh},
       {&d.Tt, (size_t)ldh * ldh},
       {&d.J, (size_t)(m + 1) * ss},
-      {&d.G, (size_t)(m + 2) * s * 2 * s},
+      {&d.G, (size_t)(m + 2) * gslot},
       {&d.G2, (size_t)(m + 2) * ss},
       {&d.Beta, ss},
       {&d.C, ss},
@@ -266,6 +275,8 @@ Krylov<T> make_krylov(lsba_context* c, int64_t n, int s, int m, const lsba_param
       {&d.M, (size_t)m * ss},
       {&d.Rinv, ss},
       {&d.P, ss},
+      {&d.RiS, (size_t)(m + 2) * ss},
+      {&d.PS, (size_t)(m + 2) * ss},
       {&d.Gv, (size_t)ldh * ldh},
       {&d.scratch, 64 * ss + 8 * big},
       {&d.coef64, (size_t)lay.total()},
@@ -296,6 +307,7 @@ Krylov<T> make_krylov(lsba_context* c, int64_t n, int s, int m, const lsba_param
   d.skel = p.skeleton;
   d.method = p.method;
   d.mixed = sizeof(T) == sizeof(float) ? 1 : 0;
+  d.gstride = per_step ? (long long)gslot : 0;
   return k;
 }
 
@@ -387,6 +399,14 @@ CycleOut run_cycles(lsba_context* c, const lsba_operator* op, const lsba_params&
     HIPCHK(hipStreamWaitEvent(side, e, 0));
     launch_small_finalize(side, d, col, tm);
   };
+  // Alg. 7: H column, J recurrence and the test of column kk - 1, off the basis path
+  auto side_after = [&](int kk, int mcur) {
+    hipEvent_t e = event();
+    HIPCHK(hipEventRecord(e, st));
+    HIPCHK(hipStreamWaitEvent(side, e, 0));
+    launch_small_side(side, d, kk, mcur, tm);
+  };
+  auto gslot = [&](int kk) { return d.G + (int64_t)kk * d.gstride; };
   auto tag = [&](int step, int phase) {
     if (tm) tm->tag(step, phase);
   };
@@ -419,15 +439,19 @@ CycleOut run_cycles(lsba_context* c, const lsba_operator* op, const lsba_params&
         tag(kk, 0);
         if (!last) launch_spmm<T>(st, n, op->nnz, s, op->rp, op->ci, val, k.U, k.W, ctl, tm);
         if (kk == 1)
-          launch_gram<T>(st, gram_args<T>(k, 1, {}, {k.W}), k.partial, d.G, ctl, tm);
+          launch_gram<T>(st, gram_args<T>(k, 1, {}, {k.W}), k.partial, gslot(kk), ctl, tm);
         else if (!last)
-          launch_gram<T>(st, gram_args<T>(k, kk - 1, {k.U}, {k.U, k.W}), k.partial, d.G, ctl,
-                         tm);
+          launch_gram<T>(st, gram_args<T>(k, kk - 1, {k.U}, {k.U, k.W}), k.partial, gslot(kk),
+                         ctl, tm);
         else
-          launch_gram<T>(st, gram_args<T>(k, kk - 1, {k.U}, {k.U}), k.partial, d.G, ctl, tm);
+          launch_gram<T>(st, gram_args<T>(k, kk - 1, {k.U}, {k.U}), k.partial, gslot(kk), ctl,
+                         tm);
         launch_small_delayed(st, d, kk, m, force, tm);
         tag(kk, 1);
-        if (kk >= 2) finalize_after(kk - 1);
+        if (kk >= 2) {
+          if (bcgs) side_after(kk, m);
+          else finalize_after(kk - 1);
+        }
         UpdateArgs<T> u = upd_args(k);
         if (kk == 1) {
           u.in2 = k.W;
@@ -515,7 +539,8 @@ CycleOut run_cycles(lsba_context* c, const lsba_operator* op, const lsba_params&
     const int cst = hc.cyc_status;
     if (tm) {
       // bytes of the basis application, known only now
-      tm->recs.back().bytes = update_bytes(uapply, hc.nv1, hc.nv2_begin, hc.nv2);
+      if (tm->on(KK_UPDATE) && !tm->recs.empty())
+        tm->recs.back().bytes = update_bytes(uapply, hc.nv1, hc.nv2_begin, hc.nv2);
       if (cst == ST_CONVERGED || cst == ST_ITERCAP)
         tm->kill_after(delayed ? j + 1 : j, false);
       else if (cst == ST_FLAGGED)
@@ -876,13 +901,13 @@ lsba_status lsba_solve(lsba_context* c, const lsba_operator* op, const lsba_para
   return r->status;
 }
 
-lsba_status lsba_context_set_timing(lsba_context* c, int enable) {
+lsba_status lsba_context_set_timing(lsba_context* c, uint32_t kind_mask) {
   if (!c) return fail(nullptr, LSBA_ERR_ARG, "context is NULL");
   try {
     (void)hipSetDevice(c->device);
     if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
     delete c->timer;
-    c->timer = enable ? new EventTimer() : nullptr;
+    c->timer = kind_mask ? new EventTimer(kind_mask) : nullptr;
   } catch (const HipError& e) {
     return fail(c, LSBA_ERR_HIP, e.msg);
   }

@@ -36,6 +36,7 @@ EXPORTS = [
 ]
 
 KERNEL_KINDS = {"spmm": 0, "gram": 1, "gram_reduce": 2, "update": 3, "small": 4, "residual": 5}
+TIME_ALL = 0x3F
 
 
 class LibraryMissing(RuntimeError):
@@ -104,7 +105,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "lsba_result_refine_steps": (i32, [vp]),
         "lsba_result_gpu_ms": (dbl, [vp]),
         "lsba_result_destroy": (None, [vp]),
-        "lsba_context_set_timing": (i32, [vp, ctypes.c_int]),
+        "lsba_context_set_timing": (i32, [vp, ctypes.c_uint32]),
         "lsba_context_kernel_stats": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                             ctypes.POINTER(dbl)]),
     }
@@ -142,8 +143,18 @@ class Context:
     def error(self) -> str:
         return self.lib.lsba_last_error(self.h).decode()
 
-    def set_timing(self, enable: bool):
-        st = self.lib.lsba_context_set_timing(self.h, 1 if enable else 0)
+    def set_timing(self, enable: bool = True, kinds=None):
+        """Time every kernel class (enable=True), the named classes (kinds, a
+        subset of KERNEL_KINDS), or nothing (enable=False)."""
+        if not enable:
+            mask = 0
+        elif kinds is None:
+            mask = TIME_ALL
+        else:
+            mask = 0
+            for k in kinds:
+                mask |= 1 << KERNEL_KINDS[k]
+        st = self.lib.lsba_context_set_timing(self.h, mask)
         if st != 0:
             raise LsbaError(st, self.error())
 
