@@ -36,8 +36,36 @@ WORKLOADS = {
                   "fp64"),
     "tridiag1000": ("tridiag1000", None, [("gmres", "bcgsi_ls")], "fp64"),
     "rgg": ("rgg", None, [("gmres", "bcgsi_ls")], "fp64"),
+    "rgg_mixed": ("rgg", None, [("gmres", "bcgsi_ls")], "mixed"),
     "laplace3d": ("laplace3d", None, [("gmres", "bcgsi_ls")], "fp64"),
+    "laplace3d_mixed": ("laplace3d", None, [("gmres", "bcgsi_ls")], "mixed"),
 }
+
+# HBM traffic of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# runs scaled by the same counters on a plain copy of known size (see
+# profiles/traffic.json); only used while the kernel source is unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = {"update": "kernels_update.hip", "gram": "kernels_gram.hip",
+                  "spmm": "kernels_sparse.hip"}
+
+
+def kernel_source_hash(kind):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2208_09899_amd", "csrc", KERNEL_SOURCES[kind])
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def stored_traffic(kind, workload):
+    """Calibrated HBM bytes per launch of kernel class `kind` on `workload`, or
+    None when no measurement of the current source exists."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kind)
+    if not k or rec.get("workload") != workload or k.get("source_sha256") != kernel_source_hash(kind):
+        return None
+    return k
 
 
 def log(*a):
@@ -193,6 +221,13 @@ def main():
             "alg_bytes_per_launch": by / launches if launches else None,
             "launches": launches,
         }
+    if "roofline" in line:
+        tr = stored_traffic(line["roofline"]["kernel"], args.workload)
+        if tr:
+            line["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
+            line["roofline"]["traffic_note"] = (
+                f"calibrated FETCH_SIZE+WRITE_SIZE per launch over {tr['launches']} launches "
+                f"(algorithmic bytes per launch in that run {tr['alg_bytes_per_launch']:.4g})")
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample ...")
         line["cpu_baseline"] = cpu_baseline(wl, solves, [r["iters"] for r in res])

@@ -1,0 +1,70 @@
+"""GPU FP64 path at the full workload sizes, in the launch configuration the
+benchmark times.
+
+The oracle cannot run whole solves at these sizes in test time, so it is
+compared on a prefix: the solve is capped at a few block iterations on both
+sides (the iteration cap ends the cycle and applies X += V Xi), and X, the
+residual-estimate history and the counts must agree as in the small parity
+tests.  Complete GPU solves are checked through properties that hold at any
+size: the recorded true residual ||B - A X||_F / ||B||_F (FP64) meets the
+tolerance, and it agrees with a host recomputation."""
+import numpy as np
+import pytest
+
+from paper_2208_09899_amd import workloads as w
+
+from gpu_common import assert_parity, gpu_solve, oracle_solve
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def laplace2d():
+    return w.workload("laplace2d")
+
+
+def test_laplace2d_256_first_cycle_matches_oracle(laplace2d):
+    """n = 65536, s = 8, m = 30: one full restart cycle (30 block columns)."""
+    wl = laplace2d
+    for method in ("gmres", "fom"):
+        g = gpu_solve(wl.A, wl.B, method=method, skeleton="bcgsi_ls", m=wl.m, tol=wl.tol,
+                      max_cycles=wl.max_cycles, max_iters=wl.m)
+        o = oracle_solve(wl.A, wl.B, method, "bcgsi_ls", m=wl.m, tol=wl.tol,
+                         max_cycles=wl.max_cycles, max_iters=wl.m)
+        assert_parity(g, o, hist_atol=1e-11)   # kappa(A) ~ 2.7e4
+
+
+@pytest.mark.parametrize("method,skel", [("gmres", "bcgsi_ls"), ("fom", "bcgsi_ls"),
+                                         ("gmres", "bmgs_cwy"), ("gmres", "bmgs_icwy")])
+def test_laplace2d_256_full_solve_true_residual(laplace2d, method, skel):
+    wl = laplace2d
+    g = gpu_solve(wl.A, wl.B, method=method, skeleton=skel, m=wl.m, tol=wl.tol,
+                  max_cycles=wl.max_cycles, true_res=True)
+    assert g.status == "ok"
+    assert g.res_hist[-1] <= wl.tol
+    true = np.linalg.norm(wl.B - wl.A.to_scipy() @ g.X) / np.linalg.norm(wl.B)
+    assert abs(g.true_relres - true) <= 1e-12
+    # the estimate of eq. normF_Rm tracks the true residual (rounding floor
+    # ~ u kappa(A) ~ 3e-12)
+    assert true <= wl.tol * (1 + 1e-3) + 1e-11, true
+
+
+def test_rgg_2pow20_first_iterations_match_oracle():
+    """n = 2^20 random geometric graph Laplacian + 1e-6 I, s = 16, m = 25:
+    the first 3 block iterations (one cycle, ended by the iteration cap)."""
+    wl = w.workload("rgg")
+    g = gpu_solve(wl.A, wl.B, method="gmres", skeleton="bcgsi_ls", m=wl.m, tol=wl.tol,
+                  max_cycles=wl.max_cycles, max_iters=3)
+    o = oracle_solve(wl.A, wl.B, "gmres", "bcgsi_ls", m=wl.m, tol=wl.tol,
+                     max_cycles=wl.max_cycles, max_iters=3)
+    assert_parity(g, o, hist_atol=1e-9)   # 10 u kappa(A), kappa ~ 1e6
+
+
+def test_laplace3d_128_first_iteration_matches_oracle():
+    """n = 128^3, s = 32, m = 20, tol 1e-10: the first block iteration."""
+    wl = w.workload("laplace3d")
+    g = gpu_solve(wl.A, wl.B, method="gmres", skeleton="bcgsi_ls", m=wl.m, tol=wl.tol,
+                  max_cycles=wl.max_cycles, max_iters=1)
+    o = oracle_solve(wl.A, wl.B, "gmres", "bcgsi_ls", m=wl.m, tol=wl.tol,
+                     max_cycles=wl.max_cycles, max_iters=1)
+    assert_parity(g, o, hist_atol=1e-11)
