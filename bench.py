@@ -109,12 +109,87 @@ def cpu_baseline(wl, solves, gpu_iters, budget_s=15.0):
     }
 
 
+def run_serving(args, torch, lsba, w):
+    """Replay the serving stream (BGMRES m = 20, tol 1e-8, BCGSI+LS + CholQR on
+    2-D convection-diffusion requests, Poisson arrivals) against a server with
+    footprint admission; latency = time from a request's arrival to its
+    fetched result."""
+    reqs = w.serving_stream(count=args.requests, rate=args.rate, seed=6)
+    log(f"[bench] building {len(reqs)} serving requests ...")
+    torch.cuda.set_device(0)
+    ctx = lsba.Context(0)
+    problems = []
+    for r in reqs:
+        A, B = w.request_problem(r)
+        problems.append((lsba.Operator(ctx, A), B))
+    params = dict(method="gmres", skeleton="bcgsi_ls", m=20, tol=1e-8, max_cycles=5000)
+    budget = 64 << 30
+    srv = lsba.Server(ctx, budget_bytes=budget, max_slots=args.slots)
+    ticket_of, arrival, finish, iters, status = {}, {}, {}, {}, {}
+    log("[bench] serving ...")
+    t0 = time.perf_counter()
+    nxt = 0
+    last_log = t0
+    while len(finish) < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and reqs[nxt].arrival <= now:
+            op, B = problems[nxt]
+            t = srv.submit(op, B, **params)
+            ticket_of[t] = nxt
+            arrival[nxt] = reqs[nxt].arrival
+            nxt += 1
+        for t in srv.poll():
+            res = srv.fetch(t)
+            i = ticket_of[t]
+            finish[i] = time.perf_counter() - t0
+            iters[i] = res.iters
+            status[i] = res.status
+        if time.perf_counter() - last_log > 20:
+            last_log = time.perf_counter()
+            log(f"[bench] {len(finish)}/{len(reqs)} done, {nxt} arrived")
+    makespan = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = np.array([finish[i] - arrival[i] for i in range(len(reqs))]) * 1e3
+    line = {
+        "metric": METRIC,
+        "value": len(reqs) / makespan,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": makespan * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"serving stream: {len(reqs)} 2-D convection-diffusion requests, "
+                                f"grid side U[64,512], Peclet U[0,10], s in {{1,4,8,16}}, "
+                                f"BGMRES m=20 tol 1e-8, Poisson arrivals at {args.rate}/s"),
+                   "slots": args.slots, "budget_bytes": budget},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(lat.mean()), "max": float(lat.max())},
+        "arrival_rate_per_s": args.rate,
+        "peak_active": st["peak_active"],
+        "iterations_total": int(sum(iters.values())),
+        "statuses": {k: sum(1 for v in status.values() if v == k) for k in set(status.values())},
+    }
+    print(json.dumps(line), flush=True)
+    for op, _ in problems:
+        op.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="laplace2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="laplace2d", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--requests", type=int, default=512, help="serving: stream length")
+    ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
+    ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not record per-kernel HIP events in the timed region")
@@ -128,6 +203,8 @@ def main():
 
     from paper_2208_09899_amd import lsba, workloads as w
 
+    if args.workload == "serving":
+        return run_serving(args, torch, lsba, w)
     key, scale, solves, precision = WORKLOADS[args.workload]
     log(f"[bench] building workload {args.workload} ...")
     wl = w.workload(key, scale)

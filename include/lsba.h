@@ -192,6 +192,63 @@ int32_t lsba_result_refine_steps(const lsba_result* r);
 double lsba_result_gpu_ms(const lsba_result* r);
 void lsba_result_destroy(lsba_result* r);
 
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of independent FP64 solves (requests) on one device.
+ * A server owns max_slots slots; each slot has its own streams, events,
+ * pinned staging memory and stream-ordered device buffers.  An admitted
+ * request keeps its basis, Hessenberg and control state on the device in its
+ * slot; its restart cycles are queued one at a time by lsba_server_poll, so
+ * the cycles of all admitted requests run concurrently on the GPU.  Requests
+ * are admitted in arrival order when a slot is free and the sum of the
+ * admitted requests' footprints (lsba_solve_footprint) stays within the byte
+ * budget.  Each request computes exactly what lsba_solve computes for it
+ * (same kernels, same fixed-order reductions): its X, histories and counts do
+ * not depend on what else runs.  Progress happens only inside
+ * lsba_server_poll; a server is used by one host thread at a time.  The
+ * operators must outlive the requests that use them. */
+typedef struct lsba_server lsba_server;
+
+/* Device bytes an FP64 solve of an n-row operator with s right-hand sides
+ * holds while it runs (B, X, basis of m + 1 blocks, U, W, Gram partials,
+ * small dense state, norm workspaces); 0 for invalid arguments. */
+uint64_t lsba_solve_footprint(int64_t n, int32_t s, const lsba_params* params);
+
+/* Create a server on ctx's device.  hbm_budget_bytes > 0 bounds the summed
+ * footprints of the admitted requests; 1 <= max_slots <= 64. */
+lsba_status lsba_server_create(lsba_context* ctx, uint64_t hbm_budget_bytes, int32_t max_slots,
+                               lsba_server** out);
+
+/* Queue a request (non-blocking).  B (n x s, row-major, ld ldb; host memory,
+ * or device memory if on_device) is copied; *ticket identifies the request.
+ * The parameters are validated as in lsba_solve; the serving form runs FP64
+ * only (LSBA_MIXED: LSBA_ERR_UNSUPPORTED).  A footprint above the budget is
+ * LSBA_ERR_OOM (it could never be admitted). */
+lsba_status lsba_server_submit(lsba_server* srv, const lsba_operator* op,
+                               const lsba_params* params, int32_t s, const double* B,
+                               int64_t ldb, int on_device, uint64_t* ticket);
+
+/* Progress engine: end the cycles whose work has completed and queue the next
+ * ones, finish requests, admit queued requests; never waits for the GPU.
+ * Writes up to cap tickets of requests finished since the last report to
+ * done[] and their number to *n_done (the rest are reported by later calls). */
+lsba_status lsba_server_poll(lsba_server* srv, uint64_t* done, int32_t cap, int32_t* n_done);
+
+/* Copy a finished request's X (n x s, ld ldx; device memory if on_device) and
+ * hand over its result (the caller destroys it with lsba_result_destroy).
+ * The ticket is then forgotten.  A request that has not finished:
+ * LSBA_ERR_BUSY; an unknown ticket: LSBA_ERR_ARG.  Returns the result's status. */
+lsba_status lsba_server_fetch(lsba_server* srv, uint64_t ticket, double* X, int64_t ldx,
+                              int on_device, lsba_result** out);
+
+/* Requests running and queued now, footprint bytes of the running ones, and
+ * the largest number of requests that ran at once. */
+lsba_status lsba_server_stats(const lsba_server* srv, int32_t* active, int32_t* queued,
+                              uint64_t* bytes_in_use, int32_t* peak_active);
+
+/* Wait for the device work of every slot and free everything, including
+ * requests not yet fetched. */
+void lsba_server_destroy(lsba_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -44,10 +46,13 @@ struct lsba_context {
   double* norm_host = nullptr; // pinned, 4
   double* stage_host = nullptr;// pinned, kMaxS * kMaxS (host-to-device staging)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev_done = nullptr;   // end of the queued cycle (no timing)
   EventTimer* timer = nullptr;   // non-null while kernel timing is enabled
   hipStream_t side = nullptr;    // second stream: per-column QR updates / convergence tests
   std::vector<hipEvent_t> evs;   // ordering events between the two streams
+  bool async_alloc = false;      // serving slots: stream-ordered allocations on `stream`
 };
+
 
 struct lsba_operator {
   lsba_context* ctx = nullptr;
@@ -201,16 +206,38 @@ struct Unsupported {
 void* ctx_buf(lsba_context* c, const std::string& name, size_t bytes) {
   auto& b = c->bufs[name];
   if (b.bytes < bytes) {
-    if (b.p) HIPCHK(hipFree(b.p));
+    if (b.p) {
+      if (c->async_alloc) HIPCHK(hipFreeAsync(b.p, c->stream));
+      else HIPCHK(hipFree(b.p));
+    }
     b.p = nullptr;
     b.bytes = 0;
-    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    const hipError_t e = c->async_alloc ? hipMallocAsync(&b.p, bytes, c->stream)
+                                        : hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
       b.p = nullptr;
-      throw HipError{"hipMalloc of " + std::to_string(bytes) + " bytes for " + name + " failed"};
+      throw HipError{"allocation of " + std::to_string(bytes) + " bytes for " + name + " failed"};
     }
     b.bytes = bytes;
   }
   return b.p;
+}
+
+// Release every cached buffer of a context (stream-ordered for serving slots).
+void ctx_release(lsba_context* c) {
+  for (auto& kv : c->bufs)
+    if (kv.second.p) {
+      if (c->async_alloc) (void)hipFreeAsync(kv.second.p, c->stream);
+      else (void)hipFree(kv.second.p);
+    }
+  c->bufs.clear();
+}
+
+// Device bytes a context's cached buffers hold.
+size_t ctx_bytes(const lsba_context* c) {
+  size_t t = 0;
+  for (const auto& kv : c->bufs) t += kv.second.bytes;
+  return t;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -228,19 +255,21 @@ struct Krylov {
   CoefLayout lay{};
 };
 
-template <typename T>
-Krylov<T> make_krylov(lsba_context* c, int64_t n, int s, int m, const lsba_params& p,
-                      const char* tag) {
+// `alloc(name, bytes)` provides device memory (the context's buffer cache, or
+// a byte counter for the serving footprint).
+template <typename T, typename Alloc>
+Krylov<T> make_krylov_with(Alloc&& alloc, int64_t n, int s, int m, const lsba_params& p,
+                           const char* tag) {
   Krylov<T> k;
   k.n = n;
   k.s = s;
   k.mmax = m;
   const std::string t(tag);
   const size_t blk = (size_t)n * s * sizeof(T);
-  k.V = (T*)ctx_buf(c, t + "V", blk * (m + 1));
-  k.U = (T*)ctx_buf(c, t + "U", blk);
-  k.W = (T*)ctx_buf(c, t + "W", blk);
-  k.partial = (double*)ctx_buf(c, t + "partial",
+  k.V = (T*)alloc(t + "V", blk * (m + 1));
+  k.U = (T*)alloc(t + "U", blk);
+  k.W = (T*)alloc(t + "W", blk);
+  k.partial = (double*)alloc(t + "partial",
                                sizeof(double) * gram_partial_doubles(n, s, m + 2, 2));
   const int ldh = (m + 1) * s;
   const size_t ss = (size_t)s * s;
@@ -287,7 +316,7 @@ Krylov<T> make_krylov(lsba_context* c, int64_t n, int s, int m, const lsba_param
   for (auto& it : items) total += align256(it.count * sizeof(double));
   const size_t coefT_bytes = align256((size_t)lay.total() * sizeof(T));
   total += coefT_bytes + align256(sizeof(Ctl));
-  char* base = (char*)ctx_buf(c, t + "dense", total);
+  char* base = (char*)alloc(t + "dense", total);
   size_t off = 0;
   for (auto& it : items) {
     *it.dst = (double*)(base + off);
@@ -309,6 +338,34 @@ Krylov<T> make_krylov(lsba_context* c, int64_t n, int s, int m, const lsba_param
   d.mixed = sizeof(T) == sizeof(float) ? 1 : 0;
   d.gstride = per_step ? (long long)gslot : 0;
   return k;
+}
+
+template <typename T>
+Krylov<T> make_krylov(lsba_context* c, int64_t n, int s, int m, const lsba_params& p,
+                      const char* tag) {
+  return make_krylov_with<T>([c](const std::string& name, size_t bytes) {
+    return ctx_buf(c, name, bytes);
+  }, n, s, m, p, tag);
+}
+
+// Device bytes one FP64 solve holds while it runs: B, X, the basis and
+// Krylov state (as make_krylov allocates it) and the norm workspaces.
+uint64_t solve_footprint(int64_t n, int s, const lsba_params& p) {
+  uint64_t tot = 0;
+  auto meas = [&tot](const std::string&, size_t bytes) -> void* {
+    tot += bytes;
+    return reinterpret_cast<void*>(uintptr_t(4096));   // never dereferenced
+  };
+  make_krylov_with<double>(meas, n, s, p.m, p, "d_");
+  const uint64_t blk64 = (uint64_t)n * s * sizeof(double);
+  tot += 2 * blk64;                                                  // B, X
+  tot += sizeof(double) * ((uint64_t)n * s / 4096 + 2) + 4 * sizeof(double);   // norm
+  if (p.record & LSBA_REC_TRUE_RES) {
+    int sh = 0;
+    while ((1 << sh) < s) ++sh;
+    tot += sizeof(double) * ((((uint64_t)n << sh) + 255) / 256 + 1);   // residual partials
+  }
+  return tot;
 }
 
 struct CycleOut {
@@ -348,71 +405,108 @@ T* slot(const Krylov<T>& k, int i) {
   return k.V + (int64_t)i * k.n * k.s;
 }
 
-// Run restart cycles of A X = R for x (zero-initialised here) in type T.
+// Restart cycles of A X = R for x (zero-initialised by begin) in type T, one
+// cycle at a time: begin() queues the set-up, enqueue() queues one whole cycle
+// (every kernel reads the device control word and returns once the cycle has
+// ended) followed by the copies of the control word and histories to pinned
+// host memory and the event c->ev_done; finish(), on the host after that
+// event, reads the cycle's outcome and returns true when the solve is over.
 template <typename T>
-CycleOut run_cycles(lsba_context* c, const lsba_operator* op, const lsba_params& p,
-                    Krylov<T>& k, const T* val, const T* rhs, T* x, double nB, double tol,
-                    lsba_result* res) {
-  hipStream_t st = c->stream;
-  const int s = k.s;
-  const int64_t n = k.n;
-  Dense& d = k.d;
-  Ctl h{};
-  h.stop = 0;
-  h.status = ST_RUNNING;
-  h.m = p.m;
-  h.max_iters = p.max_iters > 0 ? p.max_iters : 0;
-  h.nB = nB;
-  h.tol = tol;
-  h.flag_step = -1;
-  // the stream is idle here (every solve ends with a synchronisation), so the
-  // pinned staging buffers can be refilled
-  *c->ctl_host = h;
-  HIPCHK(hipMemcpyAsync(d.ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st));
-  for (int i = 0; i < s * s; ++i) c->stage_host[i] = (i / s == i % s) ? 1.0 : 0.0;
-  HIPCHK(hipMemcpyAsync(d.C, c->stage_host, sizeof(double) * s * s, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemsetAsync(x, 0, (size_t)n * s * sizeof(T), st));
-  const bool delayed = p.skeleton == LSBA_BCGSI_LS || p.skeleton == LSBA_BMGS_CWY ||
-                       p.skeleton == LSBA_BMGS_ICWY;
-  const bool bcgs = p.skeleton == LSBA_BCGSI_LS;
-  const bool rec_loo = (p.record & LSBA_REC_LOO) != 0;
-  const T* R0 = rhs;
-  int m = p.m;
+struct CycleRunner {
+  lsba_context* c;
+  const lsba_operator* op;
+  lsba_params p;
+  Krylov<T>* kp;
+  const T* val;
+  const T* rhs;
+  T* x;
+  double nB, tol;
+  lsba_result* res;
+  bool delayed = false, bcgs = false, rec_loo = false;
+  const T* R0 = nullptr;
+  int m = 0, cyc = 0;
   CycleOut out;
-  Ctl* ctl = d.ctl;
-  EventTimer* tm = c->timer;
-  hipStream_t side = c->side;
-  size_t nev = 0;
-  auto event = [&]() -> hipEvent_t {
-    if (nev == c->evs.size()) {
-      hipEvent_t e;
-      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      c->evs.push_back(e);
-    }
-    return c->evs[nev++];
-  };
-  // the per-column QR update / convergence test of column `col` runs on the
-  // side stream, after the skeleton step that made the column final
-  auto finalize_after = [&](int col) {
-    hipEvent_t e = event();
-    HIPCHK(hipEventRecord(e, st));
-    HIPCHK(hipStreamWaitEvent(side, e, 0));
-    launch_small_finalize(side, d, col, tm);
-  };
-  // Alg. 7: H column, J recurrence and the test of column kk - 1, off the basis path
-  auto side_after = [&](int kk, int mcur) {
-    hipEvent_t e = event();
-    HIPCHK(hipEventRecord(e, st));
-    HIPCHK(hipStreamWaitEvent(side, e, 0));
-    launch_small_side(side, d, kk, mcur, tm);
-  };
-  auto gslot = [&](int kk) { return d.G + (int64_t)kk * d.gstride; };
-  auto tag = [&](int step, int phase) {
-    if (tm) tm->tag(step, phase);
-  };
-  for (int cyc = 1; cyc <= p.max_cycles; ++cyc) {
+  UpdateArgs<T> uapply{};
+
+  void begin() {
+    Krylov<T>& k = *kp;
+    hipStream_t st = c->stream;
+    const int s = k.s;
+    const int64_t n = k.n;
+    Dense& d = k.d;
+    Ctl* ctl = d.ctl;
+    EventTimer* tm = c->timer;
+    (void)s;
+    (void)n;
+    (void)ctl;
+    (void)tm;
+    Ctl h{};
+    h.stop = 0;
+    h.status = ST_RUNNING;
+    h.m = p.m;
+    h.max_iters = p.max_iters > 0 ? p.max_iters : 0;
+    h.nB = nB;
+    h.tol = tol;
+    h.flag_step = -1;
+    // the stream is idle here (every solve ends with a synchronisation), so the
+    // pinned staging buffers can be refilled
+    *c->ctl_host = h;
+    HIPCHK(hipMemcpyAsync(d.ctl, c->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    for (int i = 0; i < s * s; ++i) c->stage_host[i] = (i / s == i % s) ? 1.0 : 0.0;
+    HIPCHK(hipMemcpyAsync(d.C, c->stage_host, sizeof(double) * s * s, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(x, 0, (size_t)n * s * sizeof(T), st));
+    delayed = p.skeleton == LSBA_BCGSI_LS || p.skeleton == LSBA_BMGS_CWY ||
+              p.skeleton == LSBA_BMGS_ICWY;
+    bcgs = p.skeleton == LSBA_BCGSI_LS;
+    rec_loo = (p.record & LSBA_REC_LOO) != 0;
+    R0 = rhs;
+    m = p.m;
+  }
+
+  void enqueue() {
+    Krylov<T>& k = *kp;
+    hipStream_t st = c->stream;
+    const int s = k.s;
+    const int64_t n = k.n;
+    Dense& d = k.d;
+    Ctl* ctl = d.ctl;
+    EventTimer* tm = c->timer;
+    (void)s;
+    (void)n;
+    (void)ctl;
+    (void)tm;
+    const int cyc_ = ++cyc;
+    hipStream_t side = c->side;
+    size_t nev = 0;
+    auto event = [&]() -> hipEvent_t {
+      if (nev == c->evs.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->evs.push_back(e);
+      }
+      return c->evs[nev++];
+    };
+    // the per-column QR update / convergence test of column `col` runs on the
+    // side stream, after the skeleton step that made the column final
+    auto finalize_after = [&](int col) {
+      hipEvent_t e = event();
+      HIPCHK(hipEventRecord(e, st));
+      HIPCHK(hipStreamWaitEvent(side, e, 0));
+      launch_small_finalize(side, d, col, tm);
+    };
+    // Alg. 7: H column, J recurrence and the test of column kk - 1, off the basis path
+    auto side_after = [&](int kk, int mcur) {
+      hipEvent_t e = event();
+      HIPCHK(hipEventRecord(e, st));
+      HIPCHK(hipStreamWaitEvent(side, e, 0));
+      launch_small_side(side, d, kk, mcur, tm);
+    };
+    auto gslot = [&](int kk) { return d.G + (int64_t)kk * d.gstride; };
+    auto tag = [&](int step, int phase) {
+      if (tm) tm->tag(step, phase);
+    };
     nev = 0;
-    const int fk = (p.force_flag_cycle == cyc) ? p.force_flag_step : -1;
+    const int fk = (p.force_flag_cycle == cyc_) ? p.force_flag_step : -1;
     // IntraOrtho(R0) by CholQR: V_1 = R0 B^{-1} (and U = V_1 for the delayed skeletons)
     tag(0, 0);
     launch_gram<T>(st, gram_args<T>(k, 0, {R0}, {R0}), k.partial, d.G, ctl, tm);
@@ -520,7 +614,7 @@ CycleOut run_cycles(lsba_context* c, const lsba_operator* op, const lsba_params&
     }
     tag(1 << 30, 0);
     launch_small_cycle_end(st, d, tm);
-    UpdateArgs<T> uapply = upd_args(k);
+    uapply = upd_args(k);
     uapply.in1 = x;
     uapply.out1 = x;
     uapply.out2 = k.U;
@@ -532,8 +626,21 @@ CycleOut run_cycles(lsba_context* c, const lsba_operator* op, const lsba_params&
     if (rec_loo)
       HIPCHK(hipMemcpyAsync(c->hist_host + (kMaxM + 2), d.loo_hist, sizeof(double) * (m + 1),
                             hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(c->ev_done, st));
+  }
+
+  bool finish() {
+    Krylov<T>& k = *kp;
+    hipStream_t st = c->stream;
+    const int s = k.s;
+    const int64_t n = k.n;
+    Dense& d = k.d;
+    Ctl* ctl = d.ctl;
+    EventTimer* tm = c->timer;
+    (void)s;
+    (void)n;
+    (void)ctl;
+    (void)tm;
     const Ctl& hc = *c->ctl_host;
     const int j = hc.j;
     const int cst = hc.cyc_status;
@@ -563,14 +670,60 @@ CycleOut run_cycles(lsba_context* c, const lsba_operator* op, const lsba_params&
       if (cst == ST_CONVERGED) out.status = LSBA_OK;
       else if (cst == ST_FLAGGED) out.status = LSBA_BREAKDOWN;
       else out.status = LSBA_NOT_CONVERGED;
-      return out;
+      return true;
     }
     m = hc.m;
     R0 = k.U;
+    return false;
   }
-  out.status = LSBA_NOT_CONVERGED;
-  return out;
+};
+
+template <typename T>
+CycleOut run_cycles(lsba_context* c, const lsba_operator* op, const lsba_params& p,
+                    Krylov<T>& k, const T* val, const T* rhs, T* x, double nB, double tol,
+                    lsba_result* res) {
+  CycleRunner<T> r{c, op, p, &k, val, rhs, x, nB, tol, res};
+  r.begin();
+  for (;;) {
+    if (r.cyc >= p.max_cycles) {
+      r.out.status = LSBA_NOT_CONVERGED;
+      return r.out;
+    }
+    r.enqueue();
+    HIPCHK(hipEventSynchronize(c->ev_done));
+    HIPCHK(hipGetLastError());
+    if (r.finish()) return r.out;
+  }
 }
+
+// ------------------------------------------------------------------ serving
+
+// One request of the serving form: a copy of its right-hand side, its result,
+// and host timestamps (steady clock, seconds).
+struct SrvRequest {
+  uint64_t ticket = 0;
+  const lsba_operator* op = nullptr;
+  lsba_params p{};
+  int s = 0;
+  int64_t n = 0;
+  uint64_t footprint = 0;
+  std::vector<double> B, X;
+  lsba_result* res = nullptr;
+  int state = 0;   // 0 queued, 1 running, 2 done
+};
+
+// A slot runs one admitted request on its own context (streams, events,
+// pinned staging, stream-ordered device buffers).
+struct SrvSlot {
+  lsba_context* c = nullptr;
+  SrvRequest* req = nullptr;
+  Krylov<double> k{};
+  std::unique_ptr<CycleRunner<double>> run;
+  double* B64 = nullptr;
+  double* X64 = nullptr;
+  double nB = 0.0;
+  bool in_flight = false;
+};
 
 double device_norm(lsba_context* c, const double* x, int64_t count) {
   double* partial = (double*)ctx_buf(c, "norm_partial", sizeof(double) * ((count / 4096) + 2));
@@ -601,6 +754,7 @@ double device_residual(lsba_context* c, const lsba_operator* op, int s, const do
   return c->norm_host[0];
 }
 
+
 void validate_params(const lsba_params* p, int s) {
   if (!p) throw ArgError{"params is NULL"};
   if (p->struct_size != sizeof(lsba_params)) throw ArgError{"params.struct_size mismatch"};
@@ -617,10 +771,136 @@ void validate_params(const lsba_params* p, int s) {
     throw ArgError{"mixed form needs max_refine >= 1 and inner_tol > 0"};
 }
 
+
 lsba_status fail(lsba_context* c, lsba_status st, const std::string& msg) {
   if (c) c->err = msg;
   else g_create_err = msg;
   return st;
+}
+
+}  // namespace
+
+struct lsba_server {
+  lsba_context* ctx = nullptr;
+  uint64_t budget = 0, in_use = 0;
+  int32_t peak_active = 0;
+  uint64_t next_ticket = 1;
+  std::vector<SrvSlot> slots;
+  std::deque<SrvRequest*> queue;
+  std::map<uint64_t, SrvRequest*> reqs;
+  std::deque<uint64_t> done;   // completed, not yet reported by poll
+};
+
+namespace {
+
+// Admit request r into slot sl: upload B, form ||B||_F, lay out the Krylov
+// state and queue the first cycle.
+void srv_start(lsba_server* sv, SrvSlot& sl, SrvRequest* r) {
+  lsba_context* c = sl.c;
+  hipStream_t st = c->stream;
+  const size_t blk64 = (size_t)r->n * r->s * sizeof(double);
+  sl.req = r;
+  r->state = 1;
+  sv->in_use += r->footprint;
+  sl.B64 = (double*)ctx_buf(c, "B64", blk64);
+  sl.X64 = (double*)ctx_buf(c, "X64", blk64);
+  HIPCHK(hipEventRecord(c->ev0, st));
+  HIPCHK(hipMemcpyAsync(sl.B64, r->B.data(), blk64, hipMemcpyHostToDevice, st));
+  sl.nB = device_norm(c, sl.B64, r->n * r->s);
+  r->res->have_loo = (r->p.record & LSBA_REC_LOO) != 0;
+  if (sl.nB == 0.0) {
+    HIPCHK(hipMemsetAsync(sl.X64, 0, blk64, st));
+    r->res->status = LSBA_OK;
+    r->res->true_relres = 0.0;
+    sl.run.reset();
+    HIPCHK(hipEventRecord(c->ev_done, st));
+    sl.in_flight = true;
+    return;
+  }
+  sl.k = make_krylov<double>(c, r->n, r->s, r->p.m, r->p, "d_");
+  sl.run.reset(new CycleRunner<double>{c, r->op, r->p, &sl.k, r->op->val, sl.B64, sl.X64, sl.nB,
+                                       r->p.tol, r->res});
+  sl.run->begin();
+  sl.run->enqueue();
+  sl.in_flight = true;
+}
+
+// The request in slot sl has ended: copy X out, release the slot's memory.
+void srv_complete(lsba_server* sv, SrvSlot& sl) {
+  lsba_context* c = sl.c;
+  SrvRequest* r = sl.req;
+  hipStream_t st = c->stream;
+  if (sl.run) {
+    const CycleOut& o = sl.run->out;
+    r->res->status = o.status;
+    r->res->iters = o.iters;
+    r->res->a = o.a;
+    r->res->v = o.v;
+    r->res->sy = o.sy;
+    if (r->p.record & LSBA_REC_TRUE_RES)
+      r->res->true_relres = device_residual(c, r->op, r->s, sl.X64, sl.B64, nullptr) / sl.nB;
+  }
+  const size_t blk64 = (size_t)r->n * r->s * sizeof(double);
+  r->X.resize((size_t)r->n * r->s);
+  HIPCHK(hipMemcpyAsync(r->X.data(), sl.X64, blk64, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipEventRecord(c->ev1, st));
+  HIPCHK(hipEventSynchronize(c->ev1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  r->res->gpu_ms = ms;
+  sl.run.reset();
+  ctx_release(c);
+  sv->in_use -= r->footprint;
+  r->state = 2;
+  r->B.clear();
+  r->B.shrink_to_fit();
+  sv->done.push_back(r->ticket);
+  sl.req = nullptr;
+  sl.in_flight = false;
+}
+
+// One pass of the progress engine: finish cycles whose event has completed
+// and queue the next ones, then admit queued requests in arrival order while
+// a slot is free and the byte budget allows.
+void srv_progress(lsba_server* sv) {
+  for (auto& sl : sv->slots) {
+    if (!sl.req || !sl.in_flight) continue;
+    const hipError_t q = hipEventQuery(sl.c->ev_done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) throw HipError{std::string("cycle event: ") + hipGetErrorString(q)};
+    HIPCHK(hipGetLastError());
+    sl.in_flight = false;
+    bool end = true;
+    if (sl.run) {
+      end = sl.run->finish();
+      if (!end && sl.run->cyc >= sl.req->p.max_cycles) {
+        sl.run->out.status = LSBA_NOT_CONVERGED;
+        end = true;
+      }
+    }
+    if (end) {
+      srv_complete(sv, sl);
+    } else {
+      sl.run->enqueue();
+      sl.in_flight = true;
+    }
+  }
+  while (!sv->queue.empty()) {
+    SrvRequest* r = sv->queue.front();
+    if (sv->in_use + r->footprint > sv->budget) break;
+    SrvSlot* free_slot = nullptr;
+    for (auto& sl : sv->slots)
+      if (!sl.req) {
+        free_slot = &sl;
+        break;
+      }
+    if (!free_slot) break;
+    sv->queue.pop_front();
+    srv_start(sv, *free_slot, r);
+  }
+  int32_t active = 0;
+  for (auto& sl : sv->slots) active += sl.req ? 1 : 0;
+  if (active > sv->peak_active) sv->peak_active = active;
 }
 
 }  // namespace
@@ -696,6 +976,7 @@ lsba_status lsba_context_create(int device, void* hip_stream, lsba_context** out
                          hipHostMallocDefault));
     HIPCHK(hipEventCreate(&c->ev0));
     HIPCHK(hipEventCreate(&c->ev1));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
   } catch (const HipError& e) {
     lsba_context_destroy(c);
     return fail(nullptr, LSBA_ERR_HIP, e.msg);
@@ -708,14 +989,15 @@ void lsba_context_destroy(lsba_context* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (auto& kv : c->bufs)
-    if (kv.second.p) (void)hipFree(kv.second.p);
+  ctx_release(c);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->ctl_host) (void)hipHostFree(c->ctl_host);
   if (c->hist_host) (void)hipHostFree(c->hist_host);
   if (c->norm_host) (void)hipHostFree(c->norm_host);
   if (c->stage_host) (void)hipHostFree(c->stage_host);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->ev_done) (void)hipEventDestroy(c->ev_done);
   delete c->timer;
   for (auto e : c->evs) (void)hipEventDestroy(e);
   if (c->side) {
@@ -948,5 +1230,159 @@ double lsba_result_true_relres(const lsba_result* r) { return r ? r->true_relres
 int32_t lsba_result_refine_steps(const lsba_result* r) { return r ? r->refine : 0; }
 double lsba_result_gpu_ms(const lsba_result* r) { return r ? r->gpu_ms : 0.0; }
 void lsba_result_destroy(lsba_result* r) { delete r; }
+
+uint64_t lsba_solve_footprint(int64_t n, int32_t s, const lsba_params* p) {
+  if (!p || n < 1 || s < 1 || s > kMaxS || p->m < 1 || p->m > kMaxM) return 0;
+  return solve_footprint(n, s, *p);
+}
+
+lsba_status lsba_server_create(lsba_context* c, uint64_t hbm_budget_bytes, int32_t max_slots,
+                               lsba_server** out) {
+  if (!c) return fail(nullptr, LSBA_ERR_ARG, "context is NULL");
+  if (!out || max_slots < 1 || max_slots > 64 || hbm_budget_bytes == 0)
+    return fail(c, LSBA_ERR_ARG, "need out != NULL, 1 <= max_slots <= 64, budget > 0");
+  *out = nullptr;
+  auto* sv = new (std::nothrow) lsba_server();
+  if (!sv) return fail(c, LSBA_ERR_OOM, "host allocation failed");
+  sv->ctx = c;
+  sv->budget = hbm_budget_bytes;
+  sv->slots.resize(max_slots);
+  for (auto& sl : sv->slots) {
+    const lsba_status st = lsba_context_create(c->device, nullptr, &sl.c);
+    if (st != LSBA_OK) {
+      lsba_server_destroy(sv);
+      return fail(c, st, "slot context: " + g_create_err);
+    }
+    sl.c->async_alloc = true;
+  }
+  *out = sv;
+  return LSBA_OK;
+}
+
+lsba_status lsba_server_submit(lsba_server* sv, const lsba_operator* op, const lsba_params* prm,
+                               int32_t s, const double* B, int64_t ldb, int on_device,
+                               uint64_t* ticket) {
+  if (!sv) return fail(nullptr, LSBA_ERR_ARG, "server is NULL");
+  lsba_context* c = sv->ctx;
+  if (!op || !B || !ticket) return fail(c, LSBA_ERR_ARG, "NULL pointer argument");
+  if (op->ctx != c) return fail(c, LSBA_ERR_ARG, "operator belongs to another context");
+  try {
+    validate_params(prm, s);
+    if (ldb < s) throw ArgError{"ldb must be >= s"};
+    if (prm->precision != LSBA_FP64) throw Unsupported{"the serving form runs FP64 solves"};
+  } catch (const ArgError& e) {
+    return fail(c, LSBA_ERR_ARG, e.msg);
+  } catch (const Unsupported& e) {
+    return fail(c, LSBA_ERR_UNSUPPORTED, e.msg);
+  }
+  const uint64_t fp = solve_footprint(op->n, s, *prm);
+  if (fp > sv->budget) return fail(c, LSBA_ERR_OOM, "request footprint exceeds the server budget");
+  auto* r = new (std::nothrow) SrvRequest();
+  if (!r) return fail(c, LSBA_ERR_OOM, "host allocation failed");
+  r->res = new (std::nothrow) lsba_result();
+  if (!r->res) {
+    delete r;
+    return fail(c, LSBA_ERR_OOM, "host allocation failed");
+  }
+  r->op = op;
+  r->p = *prm;
+  r->s = s;
+  r->n = op->n;
+  r->footprint = fp;
+  try {
+    r->B.resize((size_t)r->n * s);
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipMemcpy2D(r->B.data(), s * sizeof(double), B, ldb * sizeof(double),
+                       s * sizeof(double), r->n,
+                       on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+  } catch (const HipError& e) {
+    delete r->res;
+    delete r;
+    return fail(c, LSBA_ERR_HIP, e.msg);
+  } catch (const std::bad_alloc&) {
+    delete r->res;
+    delete r;
+    return fail(c, LSBA_ERR_OOM, "host allocation failed");
+  }
+  r->ticket = sv->next_ticket++;
+  sv->reqs[r->ticket] = r;
+  sv->queue.push_back(r);
+  *ticket = r->ticket;
+  return LSBA_OK;
+}
+
+lsba_status lsba_server_poll(lsba_server* sv, uint64_t* done, int32_t cap, int32_t* n_done) {
+  if (!sv) return fail(nullptr, LSBA_ERR_ARG, "server is NULL");
+  if (!n_done || cap < 0 || (cap > 0 && !done)) return fail(sv->ctx, LSBA_ERR_ARG, "bad output");
+  try {
+    HIPCHK(hipSetDevice(sv->ctx->device));
+    srv_progress(sv);
+  } catch (const HipError& e) {
+    return fail(sv->ctx, LSBA_ERR_HIP, e.msg);
+  }
+  int32_t k = 0;
+  while (k < cap && !sv->done.empty()) {
+    done[k++] = sv->done.front();
+    sv->done.pop_front();
+  }
+  *n_done = k;
+  return LSBA_OK;
+}
+
+lsba_status lsba_server_fetch(lsba_server* sv, uint64_t ticket, double* X, int64_t ldx,
+                              int on_device, lsba_result** out) {
+  if (!sv) return fail(nullptr, LSBA_ERR_ARG, "server is NULL");
+  lsba_context* c = sv->ctx;
+  if (!X || !out) return fail(c, LSBA_ERR_ARG, "NULL pointer argument");
+  *out = nullptr;
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return fail(c, LSBA_ERR_ARG, "unknown ticket");
+  SrvRequest* r = it->second;
+  if (r->state != 2) return fail(c, LSBA_ERR_BUSY, "request not finished");
+  if (ldx < r->s) return fail(c, LSBA_ERR_ARG, "ldx must be >= s");
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipMemcpy2D(X, ldx * sizeof(double), r->X.data(), r->s * sizeof(double),
+                       r->s * sizeof(double), r->n,
+                       on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+  } catch (const HipError& e) {
+    return fail(c, LSBA_ERR_HIP, e.msg);
+  }
+  *out = r->res;
+  sv->reqs.erase(it);
+  delete r;
+  return (*out)->status;
+}
+
+lsba_status lsba_server_stats(const lsba_server* sv, int32_t* active, int32_t* queued,
+                              uint64_t* bytes_in_use, int32_t* peak_active) {
+  if (!sv) return LSBA_ERR_ARG;
+  int32_t a = 0;
+  for (const auto& sl : sv->slots) a += sl.req ? 1 : 0;
+  if (active) *active = a;
+  if (queued) *queued = (int32_t)sv->queue.size();
+  if (bytes_in_use) *bytes_in_use = sv->in_use;
+  if (peak_active) *peak_active = sv->peak_active;
+  return LSBA_OK;
+}
+
+void lsba_server_destroy(lsba_server* sv) {
+  if (!sv) return;
+  for (auto& sl : sv->slots) {
+    if (sl.c) {
+      (void)hipSetDevice(sl.c->device);
+      (void)hipStreamSynchronize(sl.c->side);
+      (void)hipStreamSynchronize(sl.c->stream);
+      sl.run.reset();
+      lsba_context_destroy(sl.c);
+      sl.c = nullptr;
+    }
+  }
+  for (auto& kv : sv->reqs) {
+    delete kv.second->res;
+    delete kv.second;
+  }
+  delete sv;
+}
 
 }  // extern "C"

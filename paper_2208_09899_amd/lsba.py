@@ -33,6 +33,8 @@ EXPORTS = [
     "lsba_result_cycles", "lsba_result_cycle_len", "lsba_result_m_after", "lsba_result_counts",
     "lsba_result_true_relres", "lsba_result_refine_steps", "lsba_result_gpu_ms",
     "lsba_result_destroy", "lsba_context_set_timing", "lsba_context_kernel_stats",
+    "lsba_solve_footprint", "lsba_server_create", "lsba_server_submit", "lsba_server_poll",
+    "lsba_server_fetch", "lsba_server_stats", "lsba_server_destroy",
 ]
 
 KERNEL_KINDS = {"spmm": 0, "gram": 1, "gram_reduce": 2, "update": 3, "small": 4, "residual": 5}
@@ -108,6 +110,16 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "lsba_context_set_timing": (i32, [vp, ctypes.c_uint32]),
         "lsba_context_kernel_stats": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                             ctypes.POINTER(dbl)]),
+        "lsba_solve_footprint": (ctypes.c_uint64, [i64, i32, vp]),
+        "lsba_server_create": (i32, [vp, ctypes.c_uint64, i32, ctypes.POINTER(vp)]),
+        "lsba_server_submit": (i32, [vp, vp, vp, i32, vp, i64, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_uint64)]),
+        "lsba_server_poll": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), i32, ctypes.POINTER(i32)]),
+        "lsba_server_fetch": (i32, [vp, ctypes.c_uint64, vp, i64, ctypes.c_int,
+                                    ctypes.POINTER(vp)]),
+        "lsba_server_stats": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(i32)]),
+        "lsba_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -284,6 +296,11 @@ def solve(ctx: Context, op: Operator, B, X=None, **kw) -> Result:
                         1 if on_dev else 0, ctypes.byref(h))
     if st < 0:
         raise LsbaError(st, ctx.error())
+    return _take_result(lib, h, X)
+
+
+def _take_result(lib, h, X) -> Result:
+    """Read a library result into a Result and destroy the handle."""
     try:
         it = lib.lsba_result_iters(h)
         rp = lib.lsba_result_res_hist(h)
@@ -303,3 +320,76 @@ def solve(ctx: Context, op: Operator, B, X=None, **kw) -> Result:
                       gpu_ms=lib.lsba_result_gpu_ms(h))
     finally:
         lib.lsba_result_destroy(h)
+
+
+def footprint(n: int, s: int, **kw) -> int:
+    """Device bytes a solve of an n-row operator with s right-hand sides holds."""
+    p = make_params(**kw)
+    return int(load().lsba_solve_footprint(n, s, ctypes.byref(p)))
+
+
+class Server:
+    """Continuous batching of FP64 solves on one device (see lsba_server_* in
+    include/lsba.h): submit() queues a request, poll() advances every running
+    request by the cycles whose device work has completed and admits queued
+    ones within the byte budget, fetch() returns a finished request's result."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, max_slots: int = 8):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        h = ctypes.c_void_p()
+        st = self.lib.lsba_server_create(ctx.h, int(budget_bytes), int(max_slots), ctypes.byref(h))
+        if st != 0:
+            raise LsbaError(st, ctx.error())
+        self.h = h
+        self._shape = {}
+
+    def submit(self, op: Operator, B, **kw) -> int:
+        p = make_params(**kw)
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        n, s = B.shape
+        t = ctypes.c_uint64()
+        st = self.lib.lsba_server_submit(self.h, op.h, ctypes.byref(p), s,
+                                         B.ctypes.data_as(ctypes.c_void_p), s, 0, ctypes.byref(t))
+        if st != 0:
+            raise LsbaError(st, self.ctx.error())
+        self._shape[t.value] = (n, s)
+        return t.value
+
+    def poll(self, cap: int = 256) -> list:
+        buf = (ctypes.c_uint64 * cap)()
+        k = ctypes.c_int32()
+        st = self.lib.lsba_server_poll(self.h, buf, cap, ctypes.byref(k))
+        if st != 0:
+            raise LsbaError(st, self.ctx.error())
+        return [int(buf[i]) for i in range(k.value)]
+
+    def fetch(self, ticket: int) -> Result:
+        n, s = self._shape[ticket]
+        X = np.empty((n, s), dtype=np.float64)
+        h = ctypes.c_void_p()
+        st = self.lib.lsba_server_fetch(self.h, ticket, X.ctypes.data_as(ctypes.c_void_p), s, 0,
+                                        ctypes.byref(h))
+        if st < 0:
+            raise LsbaError(st, self.ctx.error())
+        del self._shape[ticket]
+        return _take_result(self.lib, h, X)
+
+    def stats(self) -> dict:
+        a, q, pk = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        b = ctypes.c_uint64()
+        self.lib.lsba_server_stats(self.h, ctypes.byref(a), ctypes.byref(q), ctypes.byref(b),
+                                   ctypes.byref(pk))
+        return {"active": a.value, "queued": q.value, "bytes_in_use": b.value,
+                "peak_active": pk.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lsba_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -61,3 +61,16 @@ def test_params_struct_layout_matches_header():
     offs = {name: getattr(lsba.Params, name).offset for name, _ in lsba.Params._fields_}
     assert offs["tol"] == 24 and offs["max_iters"] == 40 and offs["inner_tol"] == 56
     assert ctypes.sizeof(lsba.Params) == 80
+
+
+def test_solve_footprint_counts_the_basis(lib):
+    """lsba_solve_footprint is host-only arithmetic: at least B, X, U, W and the
+    m + 1 basis blocks, growing with n, s and m; invalid shapes give 0."""
+    from paper_2208_09899_amd import lsba
+    n, s, m = 10000, 8, 20
+    fp = lsba.footprint(n, s, m=m)
+    assert fp >= (m + 1 + 4) * n * s * 8
+    assert lsba.footprint(2 * n, s, m=m) > fp
+    assert lsba.footprint(n, 2 * s, m=m) > fp
+    assert lsba.footprint(n, s, m=m + 5) > fp
+    assert lsba.footprint(n, 33, m=m) == 0
