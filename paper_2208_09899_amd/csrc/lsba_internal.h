@@ -193,4 +193,15 @@ void launch_small_svl_z(hipStream_t st, const Dense& d, int k, KTimer* tm = null
 void launch_small_cycle_end(hipStream_t st, const Dense& d, KTimer* tm = nullptr);
 void launch_small_loo(hipStream_t st, const Dense& d, int k_new_block, KTimer* tm = nullptr);
 
+// HouseQR IntraOrtho (TSQR, FP64 inside) of the n x s block X: Q to out1 (and
+// out2 if non-null; either may alias X), R with diag(R) >= 0 to the caller's
+// state: HM_START -- the cycle start (control word, Beta, g, T = I), HM_IO --
+// Alg. 5's IntraOrtho at loop step k (H_{k+1,k}, flag at step k).  `work`
+// holds house_work_doubles(n, s) doubles.
+enum HouseMode : int { HM_START = 0, HM_IO = 1 };
+size_t house_work_doubles(int64_t n, int s);
+template <typename T>
+void launch_house(hipStream_t st, const Dense& d, int64_t n, int s, const T* X, T* out1, T* out2,
+                  double* work, int mode, int k, int force, KTimer* tm = nullptr);
+
 }  // namespace lsba

@@ -251,6 +251,7 @@ struct Krylov {
   T* U = nullptr;
   T* W = nullptr;
   double* partial = nullptr;
+  double* hwork = nullptr;   // HouseQR muscle: TSQR workspace
   Dense d{};
   CoefLayout lay{};
 };
@@ -271,6 +272,8 @@ Krylov<T> make_krylov_with(Alloc&& alloc, int64_t n, int s, int m, const lsba_pa
   k.W = (T*)alloc(t + "W", blk);
   k.partial = (double*)alloc(t + "partial",
                                sizeof(double) * gram_partial_doubles(n, s, m + 2, 2));
+  if (p.muscle == LSBA_HOUSEQR)
+    k.hwork = (double*)alloc(t + "hwork", sizeof(double) * house_work_doubles(n, s));
   const int ldh = (m + 1) * s;
   const size_t ss = (size_t)s * s;
   const size_t big = (size_t)(m + 2) * ss;
@@ -509,10 +512,15 @@ struct CycleRunner {
     const int fk = (p.force_flag_cycle == cyc_) ? p.force_flag_step : -1;
     // IntraOrtho(R0) by CholQR: V_1 = R0 B^{-1} (and U = V_1 for the delayed skeletons)
     tag(0, 0);
-    launch_gram<T>(st, gram_args<T>(k, 0, {R0}, {R0}), k.partial, d.G, ctl, tm);
-    launch_small_start(st, d, fk == 0 ? 1 : 0, tm);
-    tag(0, 1);
-    {
+    if (p.muscle == LSBA_HOUSEQR) {
+      // V_1 (and U) = Q of the TSQR, Beta = R with diag(R) >= 0
+      launch_house<T>(st, d, n, s, R0, slot(k, 0), delayed ? k.U : (T*)nullptr, k.hwork,
+                      HM_START, 0, fk == 0 ? 1 : 0, tm);
+      tag(0, 1);
+    } else {
+      launch_gram<T>(st, gram_args<T>(k, 0, {R0}, {R0}), k.partial, d.G, ctl, tm);
+      launch_small_start(st, d, fk == 0 ? 1 : 0, tm);
+      tag(0, 1);
       UpdateArgs<T> u = upd_args(k);
       u.in1 = R0;
       u.out1 = slot(k, 0);
@@ -586,11 +594,16 @@ struct CycleRunner {
           u.nv2 = kk;
           launch_update<T>(st, u, ctl, true, tm);
         }
-        launch_gram<T>(st, gram_args<T>(k, 0, {slot(k, kk)}, {slot(k, kk)}), k.partial, d.G2,
-                       ctl, tm);
-        launch_small_svl_io(st, d, kk, force, tm);
-        tag(kk, 1);
-        {
+        if (p.muscle == LSBA_HOUSEQR) {
+          // IntraOrtho of the projected block in place; H_{kk+1,kk} = R
+          launch_house<T>(st, d, n, s, slot(k, kk), slot(k, kk), (T*)nullptr, k.hwork, HM_IO, kk,
+                          force, tm);
+          tag(kk, 1);
+        } else {
+          launch_gram<T>(st, gram_args<T>(k, 0, {slot(k, kk)}, {slot(k, kk)}), k.partial, d.G2,
+                         ctl, tm);
+          launch_small_svl_io(st, d, kk, force, tm);
+          tag(kk, 1);
           UpdateArgs<T> u = upd_args(k);
           u.in1 = slot(k, kk);
           u.out1 = slot(k, kk);
@@ -766,7 +779,6 @@ void validate_params(const lsba_params* p, int s) {
   if (p->precision != LSBA_FP64 && p->precision != LSBA_MIXED) throw ArgError{"bad precision"};
   if (!(p->tol >= 0.0)) throw ArgError{"tol must be >= 0"};
   if (p->max_cycles < 1) throw ArgError{"max_cycles must be >= 1"};
-  if (p->muscle == LSBA_HOUSEQR) throw Unsupported{"HouseQR muscle is not available in this build"};
   if (p->precision == LSBA_MIXED && (p->max_refine < 1 || !(p->inner_tol > 0.0)))
     throw ArgError{"mixed form needs max_refine >= 1 and inner_tol > 0"};
 }

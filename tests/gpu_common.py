@@ -24,8 +24,8 @@ def gpu_solve(csr, B, **kw):
 
 
 def oracle_solve(csr, B, method="gmres", skeleton="bcgsi_ls", m=20, tol=1e-8, max_cycles=50,
-                 max_iters=0, record_loo=False, force_flag=None):
-    return oracle.solve(csr.to_scipy(), B, method, skeleton, "cholqr", m=m, tol=tol,
+                 max_iters=0, record_loo=False, force_flag=None, muscle="cholqr"):
+    return oracle.solve(csr.to_scipy(), B, method, skeleton, muscle, m=m, tol=tol,
                         max_cycles=max_cycles, record_loo=record_loo,
                         force_flag=[force_flag] if force_flag else (),
                         max_iters=max_iters if max_iters > 0 else None)
