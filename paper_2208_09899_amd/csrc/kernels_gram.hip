@@ -171,6 +171,83 @@ __global__ __launch_bounds__(256) void gram_stage2(const double* __restrict__ pa
   }
 }
 
+
+// FP64 matrix-core variant for s a multiple of 16: a wavefront owns a 16 x 16
+// output tile (16 left columns of one block, 16 right columns of one block)
+// for a chunk of rows and feeds v_mfma_f64_16x16x4f64 four rows at a time:
+// lane l supplies left[row + l/16][i0 + l%16] and right[row + l/16][j0 + l%16]
+// (a wavefront's loads are four 128-byte row segments per operand) and holds
+// D[4 q + l/16][l%16], q < 4, of the tile.  The matrix core accumulates
+// over the rows, so no cross-lane reduction is needed, and a row element is
+// re-read from L2 only by the few tiles that share its block.  Eight row
+// groups of loads are in flight per lane.
+typedef double gd4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void gram_mfma_f64(GramArgs<double> a, int nchunk, int ngroup,
+                                                     int64_t rows_per_chunk,
+                                                     double* __restrict__ partial,
+                                                     const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->stop) return;
+  const int pid = blockIdx.x;
+  const int xcd = pid % kXcds, t = pid / kXcds;
+  const int chunk = xcd + kXcds * (t / ngroup);
+  const int grp = t % ngroup;
+  if (chunk >= nchunk) return;
+  const int s = a.s;
+  const int PA = (a.nv + a.nxl) * s, QB = a.nxr * s;
+  const int tcols = QB / 16;
+  const int ntile = (PA / 16) * tcols;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tile = grp * 4 + wave;
+  if (tile >= ntile) return;
+  const int i0 = (tile / tcols) * 16, j0 = (tile % tcols) * 16;
+  const int lr = lane & 15, lk = lane >> 4;
+  const double* __restrict__ L = left_ptr(a, i0 / s) + (i0 % s) + lr;
+  const double* __restrict__ R = a.xr[j0 / s] + (j0 % s) + lr;
+  const int64_t r0 = (int64_t)chunk * rows_per_chunk;
+  const int64_t r1 = r0 + rows_per_chunk < a.n ? r0 + rows_per_chunk : a.n;
+  gd4 acc = {0.0, 0.0, 0.0, 0.0};
+  constexpr int U = 8;   // row groups of 4 in flight
+  for (int64_t rb = r0; rb < r1; rb += 4 * U) {
+    double av[U], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = rb + 4 * u + lk;
+      const int64_t rr = row < r1 ? row : r1 - 1;   // in-bounds address, zero weight past r1
+      av[u] = L[rr * s];
+      bv[u] = R[rr * s];
+      av[u] = row < r1 ? av[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+  }
+  double* out = partial + (int64_t)chunk * PA * QB;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[(int64_t)(i0 + 4 * q + lk) * QB + j0 + lr] = acc[q];
+}
+
+struct MPlan {
+  int nchunk, ngroup;
+  int64_t rows;
+};
+
+// About 2048 workgroups (eight resident waves per SIMD), chunks of at least
+// 256 rows.
+MPlan mplan(int64_t n, int PA, int QB) {
+  MPlan p;
+  const int ntile = (PA / 16) * (QB / 16);
+  p.ngroup = (ntile + 3) / 4;
+  int64_t nchunk = 2048 / p.ngroup;
+  const int64_t maxc = (n + 255) / 256;
+  if (nchunk > maxc) nchunk = maxc;
+  if (nchunk < 1) nchunk = 1;
+  p.rows = (n + nchunk - 1) / nchunk;
+  p.nchunk = (int)((n + p.rows - 1) / p.rows);
+  return p;
+}
+
+bool use_mfma(int s) { return s % 16 == 0; }
+
 struct Plan {
   int tl, nchunk, ngroup;
   int64_t rows;
@@ -206,10 +283,26 @@ size_t gram_partial_doubles(int64_t n, int s, int nleft, int nright) {
   for (int nl = 1; nl <= nleft; ++nl)
     for (int nr = 1; nr <= nright; ++nr) {
       const Plan p = plan(n, s, nl * s, nr * s);
-      const size_t need = (size_t)p.nchunk * (size_t)(nl * s) * (size_t)(nr * s);
+      size_t need = (size_t)p.nchunk * (size_t)(nl * s) * (size_t)(nr * s);
+      if (use_mfma(s)) {
+        const MPlan q = mplan(n, nl * s, nr * s);
+        const size_t nm = (size_t)q.nchunk * (size_t)(nl * s) * (size_t)(nr * s);
+        if (nm > need) need = nm;
+      }
       if (need > best) best = need;
     }
   return best;
+}
+
+static void launch_stage2(hipStream_t st, const double* partial, int nchunk, int entries,
+                          double* out, const Ctl* ctl, KTimer* tm) {
+  // entries per workgroup: 8 .. 64, aiming at >= 256 workgroups
+  int ewl = 3;
+  while (ewl < 6 && ((entries + (1 << ewl) - 1) >> ewl) > 256) ++ewl;
+  if (tm) tm->begin(st, KK_GRAM_REDUCE);
+  gram_stage2<<<dim3((entries + (1 << ewl) - 1) >> ewl), dim3(256), 0, st>>>(
+      partial, nchunk, entries, ewl, out, ctl);
+  if (tm) tm->end(st, KK_GRAM_REDUCE, 0.0);
 }
 
 // Distinct input blocks of a Gram launch (a right block that is also a left
@@ -231,6 +324,18 @@ template <typename T>
 void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* out,
                  const Ctl* ctl, KTimer* tm) {
   const int PA = (a.nv + a.nxl) * a.s, QB = a.nxr * a.s;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    if (use_mfma(a.s)) {
+      const MPlan q = mplan(a.n, PA, QB);
+      const int nchunk_pad = ((q.nchunk + kXcds - 1) / kXcds) * kXcds;
+      if (tm) tm->begin(st, KK_GRAM);
+      gram_mfma_f64<<<dim3(nchunk_pad * q.ngroup), dim3(256), 0, st>>>(
+          a, q.nchunk, q.ngroup, q.rows, partial, ctl);
+      if (tm) tm->end(st, KK_GRAM, (double)distinct_blocks(a) * a.n * a.s * sizeof(T));
+      launch_stage2(st, partial, q.nchunk, PA * QB, out, ctl, tm);
+      return;
+    }
+  }
   const Plan p = plan(a.n, a.s, PA, QB);
   const int nchunk_pad = ((p.nchunk + kXcds - 1) / kXcds) * kXcds;
   const int blocks = nchunk_pad * p.ngroup;
@@ -253,14 +358,7 @@ void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* 
                                                             partial, ctl);
   }
   if (tm) tm->end(st, KK_GRAM, (double)distinct_blocks(a) * a.n * a.s * sizeof(T));
-  const int entries = PA * QB;
-  // entries per workgroup: 8 .. 64, aiming at >= 256 workgroups
-  int ewl = 3;
-  while (ewl < 6 && ((entries + (1 << ewl) - 1) >> ewl) > 256) ++ewl;
-  if (tm) tm->begin(st, KK_GRAM_REDUCE);
-  gram_stage2<<<dim3((entries + (1 << ewl) - 1) >> ewl), dim3(256), 0, st>>>(
-      partial, p.nchunk, entries, ewl, out, ctl);
-  if (tm) tm->end(st, KK_GRAM_REDUCE, 0.0);
+  launch_stage2(st, partial, p.nchunk, PA * QB, out, ctl, tm);
 }
 template void launch_gram<double>(hipStream_t, const GramArgs<double>&, double*, double*,
                                   const Ctl*, KTimer*);
