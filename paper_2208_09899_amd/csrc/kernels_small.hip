@@ -315,6 +315,198 @@ __global__ __launch_bounds__(NT) void small_core_kernel(Dense d, int k, int m, i
   publish_coef(d);
 }
 
+// LDS layout of small_cwy (Alg. 6, 2 <= k <= m): small matrices, Y R^{-1},
+// [Z; P] R^{-1}, H_{1:k,k}, the new T column, then the Gram output (dead
+// once Y R^{-1} and [Z; P] R^{-1} exist) and the staging area for T.
+__host__ __device__ inline int cwy_fixed(int s, int k) {
+  const int ss = s * s, r0 = (k - 1) * s, ks = k * s;
+  return 4 * ss + kMaxS + r0 * s + ks * s + ks * s + r0 * s;
+}
+__host__ __device__ inline bool cwy_fits(int s, int k) {
+  const int r0 = (k - 1) * s, ks = k * s;
+  const int g = ks * 2 * s;
+  const int stage_min = r0 * s > g ? r0 * s : g;
+  return cwy_fixed(s, k) + stage_min <= LDS_DBL;
+}
+
+// Alg. 6 (BMGS-CWY / BMGS-ICWY), loop step 2 <= k <= m, all operands in LDS.
+// From [Y Z; Omega P~] = [V_{1:k-1} U]^T [U W]: R = chol(Omega) = H_{k,k-1}
+// (flag), P = R^{-T} P~, the new T column T_{1:k-1,k} = -T (Y R^{-1}) (CWY) or
+// Y R^{-1} (ICWY), H_{1:k,k} = T^T ([Z; P] R^{-1}) (CWY) or T^{-T} ([Z; P]
+// R^{-1}) (ICWY) with T = T_{1:k,1:k}, and the coefficients of V_k = U R^{-1}
+// and U = W R^{-1} - V_{1:k} H_{1:k,k}.  T is read from global memory once,
+// staged in LDS a few rows (CWY) or column blocks (ICWY) at a time.
+template <bool ICWY>
+__global__ __launch_bounds__(NT) void small_cwy_kernel(Dense d, int k, int force) {
+  __shared__ double lds[LDS_DBL];
+  Ctl* ctl = d.ctl;
+  if (ctl->stop) return;
+  const int s = d.s, ld = d.ldh, ss = s * s;
+  CoefLayout lay{s, d.mmax + 1};
+  const int r0 = (k - 1) * s, ks = k * s, ldg = 2 * s;
+  const double* Gk = d.G + (int64_t)k * d.gstride;
+  double* Om = lds;
+  double* R = Om + ss;
+  double* Ri = R + ss;
+  double* Pn = Ri + ss;
+  double* dinv = Pn + ss;
+  double* YR = dinv + kMaxS;     // r0 x s
+  double* ZPR = YR + r0 * s;     // ks x s
+  double* Hc = ZPR + ks * s;     // ks x s
+  double* Tc = Hc + ks * s;      // r0 x s
+  double* G = Tc + r0 * s;       // ks x 2s, then the staging area
+  double* Ts = G;
+  const int tcap = LDS_DBL - (int)(G - lds);
+  bcopy(Gk, G, ks * ldg);
+  bar();
+  for (int e = threadIdx.x; e < ss; e += NT) Om[e] = G[(r0 + e / s) * ldg + (e % s)];
+  bar();
+  bool ok = chol_flag(d, Om, s, R, dinv);
+  if (force) ok = false;
+  if (!ok) {
+    if (threadIdx.x == 0) raise_flag(ctl, k, k - 2);
+    return;
+  }
+  tri_inv_up(R, s, Ri, dinv);
+  double* coef = d.coef64;
+  for (int e = threadIdx.x; e < ss; e += NT) {
+    d.H[(int64_t)(r0 + e / s) * ld + (k - 2) * s + (e % s)] = R[e];
+    coef[lay.C1() + e] = Ri[e];
+    coef[lay.C2() + e] = Ri[e];
+    const int i = e / s, c = e % s;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < s; ++t) acc = fma(Ri[t * s + i], G[(r0 + t) * ldg + s + c], acc);
+    Pn[e] = acc;   // P = R^{-T} P~
+  }
+  rows_x_small(r0, s, G, ldg, Ri, 1.0, YR, s);        // Y R^{-1}
+  rows_x_small(r0, s, G + s, ldg, Ri, 1.0, ZPR, s);   // Z R^{-1}
+  bar();
+  rows_x_small(s, s, Pn, s, Ri, 1.0, ZPR + r0 * s, s);   // P R^{-1}
+  for (int e = threadIdx.x; e < r0 * s; e += NT) Tc[e] = ICWY ? YR[e] : 0.0;
+  for (int e = threadIdx.x; e < ks * s; e += NT) Hc[e] = 0.0;
+  bar();   // the Gram output is dead from here on: G becomes the staging area
+  if (!ICWY) {
+    // T_{1:k-1,1:k-1} is block upper triangular (identity diagonal blocks):
+    // rows [t0, t1) restricted to columns [t0, r0) hold all of its nonzeros.
+    for (int t0 = 0; t0 < r0;) {
+      const int w = r0 - t0;
+      int t1 = t0 + s;
+      while (t1 + s <= r0 && (t1 + s - t0) * w <= tcap) t1 += s;
+      const int tot = (t1 - t0) * w;
+      for (int base = threadIdx.x; base < tot; base += NT * 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          int e = base + u * NT;
+          e = e < tot ? e : tot - 1;
+          v[u] = d.T[(int64_t)(t0 + e / w) * ld + t0 + (e % w)];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int e = base + u * NT;
+          if (e < tot) Ts[e] = v[u];
+        }
+      }
+      bar();
+      // Tc(t) -= T(t, t0:r0) YR(t0:r0)   for t in [t0, t1)
+      for (int e = threadIdx.x; e < (t1 - t0) * s; e += NT) {
+        const int tr = e / s, c = e % s;
+        const double* trow = Ts + tr * w;
+        double a0 = 0.0, a1 = 0.0;
+        int u = 0;
+#pragma unroll 4
+        for (; u + 1 < w; u += 2) {
+          a0 = fma(trow[u], YR[(t0 + u) * s + c], a0);
+          a1 = fma(trow[u + 1], YR[(t0 + u + 1) * s + c], a1);
+        }
+        if (u < w) a0 = fma(trow[u], YR[(t0 + u) * s + c], a0);
+        Tc[(t0 + tr) * s + c] -= a0 + a1;
+      }
+      // Hc(a) += T(t0:t1, a)^T ZPR(t0:t1)   for a in [t0, r0)
+      for (int e = threadIdx.x; e < w * s; e += NT) {
+        const int a = e / s, c = e % s;
+        double a0 = 0.0;
+#pragma unroll 4
+        for (int tr = 0; tr < t1 - t0; ++tr) a0 = fma(Ts[tr * w + a], ZPR[(t0 + tr) * s + c], a0);
+        Hc[(t0 + a) * s + c] += a0;
+      }
+      bar();
+      t0 = t1;
+    }
+    // last block row of T^T: [Tc^T, I]
+    for (int e = threadIdx.x; e < ss; e += NT) {
+      const int i = e / s, c = e % s;
+      double a0 = ZPR[(r0 + i) * s + c];
+      for (int t = 0; t < r0; ++t) a0 = fma(Tc[t * s + i], ZPR[t * s + c], a0);
+      Hc[(r0 + i) * s + c] = a0;
+    }
+    bar();
+  } else {
+    // block forward substitution with T^T (unit block lower triangular):
+    // X_b = ZPR_b - T(0:bs, bs:bs+s)^T X(0:bs), b = 0 .. k-1; column block
+    // k-1 of T is Tc (= Y R^{-1}), the others are staged from global memory.
+    for (int e = threadIdx.x; e < ss; e += NT) Hc[e] = ZPR[e];
+    bar();
+    for (int b0 = 1; b0 < k;) {
+      // stage column blocks [b0, b1) of rows [0, (b1-1) s) (up to block k-2)
+      int b1 = b0 + 1;
+      while (b1 < k - 1 && (b1 * s) * ((b1 + 1 - b0) * s) <= tcap) ++b1;
+      if (b0 >= k - 1) b1 = k;   // only the new column block is left
+      const int w = (b1 - b0) * s;
+      const int rows = (b1 - 1) * s;
+      const bool global_part = b0 < k - 1;
+      if (global_part) {
+        const int wg = ((b1 < k - 1 ? b1 : k - 1) - b0) * s;
+        const int tot = rows * wg;
+        for (int base = threadIdx.x; base < tot; base += NT * 16) {
+          double v[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            int e = base + u * NT;
+            e = e < tot ? e : tot - 1;
+            v[u] = d.T[(int64_t)(e / wg) * ld + b0 * s + (e % wg)];
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int e = base + u * NT;
+            if (e < tot) Ts[(e / wg) * w + (e % wg)] = v[u];
+          }
+        }
+        bar();
+      }
+      for (int b = b0; b < b1; ++b) {
+        const double* Tcol;
+        int ldt;
+        if (b == k - 1) {
+          Tcol = Tc;
+          ldt = s;
+        } else {
+          Tcol = Ts + (b - b0) * s;
+          ldt = w;
+        }
+        mm_t<true, false>(s, s, b * s, -1.0, Tcol, ldt, Hc, s, 0.0, Hc + b * ss, s,
+                          ZPR + b * ss, s);
+      }
+      b0 = b1;
+    }
+  }
+  // H_{1:k,k}, the new T column (and its transpose), the update coefficients
+  for (int e = threadIdx.x; e < ks * s; e += NT) {
+    const int i = e / s, c = e % s;
+    d.H[(int64_t)i * ld + (k - 1) * s + c] = Hc[e];
+    if (i < r0) coef[lay.B(0) + e] = -Hc[e];
+    else coef[lay.D() + e - r0 * s] = -Hc[e];
+  }
+  for (int e = threadIdx.x; e < r0 * s; e += NT) {
+    const int i = e / s, c = e % s;
+    d.T[(int64_t)i * ld + r0 + c] = Tc[e];
+    d.Tt[(int64_t)(r0 + c) * ld + i] = Tc[e];
+  }
+  bar();
+  publish_coef(d);
+}
+
 // Alg. 5, after Y = V_{1:k}^T W: H_{1:k,k} = T^T Y (SVL) or T^{-T} Y (LTS); the
 // projection W - V_{1:k} H_{1:k,k} is written by the next block update.
 __global__ __launch_bounds__(NT) void small_svl_y_kernel(Dense d, int k) {
@@ -418,6 +610,13 @@ void launch_small_start(hipStream_t st, const Dense& d, int force_flag, KTimer* 
 }
 void launch_small_delayed(hipStream_t st, const Dense& d, int k, int m, int force_flag,
                           KTimer* tm) {
+  if (d.skel != LSBA_BCGSI_LS && k >= 2 && k <= m && cwy_fits(d.s, k)) {
+    if (d.skel == LSBA_BMGS_ICWY)
+      SMALL_LAUNCH(small_cwy_kernel<true><<<1, NT, 0, st>>>(d, k, force_flag));
+    else
+      SMALL_LAUNCH(small_cwy_kernel<false><<<1, NT, 0, st>>>(d, k, force_flag));
+    return;
+  }
   if (d.skel == LSBA_BCGSI_LS && k >= 2) {
     const int s = d.s, ldg = (k == m + 1) ? s : 2 * s;
     if (k * s * ldg <= LDS_DBL - (5 * s * s + kMaxS))
