@@ -172,9 +172,9 @@ __global__ __launch_bounds__(256) void gram_stage2(const double* __restrict__ pa
 }
 
 
-// FP64 matrix-core variant for s a multiple of 16: a wavefront owns a 16 x 16
-// output tile (16 left columns of one block, 16 right columns of one block)
-// for a chunk of rows and feeds v_mfma_f64_16x16x4f64 four rows at a time:
+// FP64 matrix-core variant (s >= 8): a wavefront owns a 16 x 16 output tile
+// (16 consecutive left columns and 16 consecutive right columns, which may
+// span several blocks: each lane addresses its own column) for a chunk of rows and feeds v_mfma_f64_16x16x4f64 four rows at a time:
 // lane l supplies left[row + l/16][i0 + l%16] and right[row + l/16][j0 + l%16]
 // (a wavefront's loads are four 128-byte row segments per operand) and holds
 // D[4 q + l/16][l%16], q < 4, of the tile.  The matrix core accumulates
@@ -195,15 +195,19 @@ __global__ __launch_bounds__(256) void gram_mfma_f64(GramArgs<double> a, int nch
   if (chunk >= nchunk) return;
   const int s = a.s;
   const int PA = (a.nv + a.nxl) * s, QB = a.nxr * s;
-  const int tcols = QB / 16;
-  const int ntile = (PA / 16) * tcols;
+  const int tcols = (QB + 15) / 16;
+  const int ntile = ((PA + 15) / 16) * tcols;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tile = grp * 4 + wave;
   if (tile >= ntile) return;
   const int i0 = (tile / tcols) * 16, j0 = (tile % tcols) * 16;
   const int lr = lane & 15, lk = lane >> 4;
-  const double* __restrict__ L = left_ptr(a, i0 / s) + (i0 % s) + lr;
-  const double* __restrict__ R = a.xr[j0 / s] + (j0 % s) + lr;
+  // this lane's left and right columns (zero weight past PA / QB)
+  const int ci = i0 + lr, cj = j0 + lr;
+  const double wl = ci < PA ? 1.0 : 0.0, wr = cj < QB ? 1.0 : 0.0;
+  const int cic = ci < PA ? ci : PA - 1, cjc = cj < QB ? cj : QB - 1;
+  const double* __restrict__ L = left_ptr(a, cic / s) + (cic % s);
+  const double* __restrict__ R = a.xr[cjc / s] + (cjc % s);
   const int64_t r0 = (int64_t)chunk * rows_per_chunk;
   const int64_t r1 = r0 + rows_per_chunk < a.n ? r0 + rows_per_chunk : a.n;
   gd4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -216,14 +220,18 @@ __global__ __launch_bounds__(256) void gram_mfma_f64(GramArgs<double> a, int nch
       const int64_t rr = row < r1 ? row : r1 - 1;   // in-bounds address, zero weight past r1
       av[u] = L[rr * s];
       bv[u] = R[rr * s];
-      av[u] = row < r1 ? av[u] : 0.0;
+      av[u] = row < r1 ? av[u] * wl : 0.0;
+      bv[u] = bv[u] * wr;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
   }
   double* out = partial + (int64_t)chunk * PA * QB;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) out[(int64_t)(i0 + 4 * q + lk) * QB + j0 + lr] = acc[q];
+  for (int q = 0; q < 4; ++q) {
+    const int i = i0 + 4 * q + lk;
+    if (i < PA && cj < QB) out[(int64_t)i * QB + cj] = acc[q];
+  }
 }
 
 struct MPlan {
@@ -235,7 +243,7 @@ struct MPlan {
 // 256 rows.
 MPlan mplan(int64_t n, int PA, int QB) {
   MPlan p;
-  const int ntile = (PA / 16) * (QB / 16);
+  const int ntile = ((PA + 15) / 16) * ((QB + 15) / 16);
   p.ngroup = (ntile + 3) / 4;
   int64_t nchunk = 2048 / p.ngroup;
   const int64_t maxc = (n + 255) / 256;
@@ -246,7 +254,7 @@ MPlan mplan(int64_t n, int PA, int QB) {
   return p;
 }
 
-bool use_mfma(int s) { return s % 16 == 0; }
+bool use_mfma(int s) { return s >= 8; }
 
 struct Plan {
   int tl, nchunk, ngroup;

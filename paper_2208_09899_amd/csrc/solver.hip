@@ -491,18 +491,35 @@ struct CycleRunner {
     };
     // the per-column QR update / convergence test of column `col` runs on the
     // side stream, after the skeleton step that made the column final
-    auto finalize_after = [&](int col) {
+    // Off-path work (QR update / estimate / convergence test, and for Alg. 7
+    // the H column and J recurrence) is queued on the side stream in batches
+    // of kSideBatch loop steps behind one event: each step's inputs sit in
+    // their own slots, and fewer event records keep the basis-path kernels
+    // back to back.
+    struct SideJob {
+      int kind, arg, mcur;   // 0: finalize column arg; 1: Alg. 7 side step arg
+    };
+    std::vector<SideJob> pending;
+    constexpr int kSideBatch = 4;
+    auto flush_side = [&]() {
+      if (pending.empty()) return;
       hipEvent_t e = event();
       HIPCHK(hipEventRecord(e, st));
       HIPCHK(hipStreamWaitEvent(side, e, 0));
-      launch_small_finalize(side, d, col, tm);
+      for (const SideJob& j : pending) {
+        if (j.kind == 0) launch_small_finalize(side, d, j.arg, tm);
+        else launch_small_side(side, d, j.arg, j.mcur, tm);
+      }
+      pending.clear();
+    };
+    auto finalize_after = [&](int col) {
+      pending.push_back({0, col, 0});
+      if ((int)pending.size() >= kSideBatch) flush_side();
     };
     // Alg. 7: H column, J recurrence and the test of column kk - 1, off the basis path
     auto side_after = [&](int kk, int mcur) {
-      hipEvent_t e = event();
-      HIPCHK(hipEventRecord(e, st));
-      HIPCHK(hipStreamWaitEvent(side, e, 0));
-      launch_small_side(side, d, kk, mcur, tm);
+      pending.push_back({1, kk, mcur});
+      if ((int)pending.size() >= kSideBatch) flush_side();
     };
     auto gslot = [&](int kk) { return d.G + (int64_t)kk * d.gstride; };
     auto tag = [&](int step, int phase) {
@@ -620,6 +637,7 @@ struct CycleRunner {
       }
     }
     // join the side stream, then end the cycle
+    flush_side();
     {
       hipEvent_t e = event();
       HIPCHK(hipEventRecord(e, side));
