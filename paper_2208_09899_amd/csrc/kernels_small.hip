@@ -237,6 +237,7 @@ __global__ __launch_bounds__(NT) void small_delayed_kernel(Dense d, int k, int m
     }
     bar();
     set_coef(d, lay.D(), Hc + (int64_t)r0 * ld, ld, -1.0);
+    fold_coef(d, 0, 0, k - 1);
   }
   bar();
   publish_coef(d);
@@ -312,6 +313,7 @@ __global__ __launch_bounds__(NT) void small_core_kernel(Dense d, int k, int m, i
     for (int e = threadIdx.x; e < ss; e += NT) d.PS[(int64_t)k * ss + e] = Pn[e];
   }
   bar();
+  if (!last) fold_coef(d, k - 1, 0, k - 1);
   publish_coef(d);
 }
 
@@ -504,6 +506,7 @@ __global__ __launch_bounds__(NT) void small_cwy_kernel(Dense d, int k, int force
     d.Tt[(int64_t)(r0 + c) * ld + i] = Tc[e];
   }
   bar();
+  fold_coef(d, 0, 0, k - 1);
   publish_coef(d);
 }
 

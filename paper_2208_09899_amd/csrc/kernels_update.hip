@@ -167,12 +167,124 @@ __global__ __launch_bounds__(256) void update_kernel(UpdateArgs<T> a, const Ctl*
   }
 }
 
+
+// FP64, s = 8, on the matrix cores: [out1 | out2] (16 columns) is one product
+// of the inputs (in1, the basis blocks, in2; 8 columns each) with the
+// stacked coefficient rows [C1 | C1 D], [A_i | B_i + A_i D], [0 | C2] (the
+// folded D term; without D: [C1 | 0], [A_i | B_i], [0 | C2]).  A wavefront
+// owns 16 rows: for input q and K-step h, lane l supplies input row
+// (row0 + l%16), column 4h + l/16, and coefficient row 4h + l/16, column l%16;
+// v_mfma_f64_16x16x4f64 accumulates and lane l ends with rows
+// 4r + l/16 (r < 4) of output column l%16.  No LDS: the coefficients are
+// read through L1, and four inputs' loads are in flight per lane.
+typedef double ud4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ const double* mf_coef(const UpdateArgs<double>& a, const InputSeq<double>& in,
+                                                 int q, int lr, bool fold) {
+  const CoefLayout& lay = a.lay;
+  const double* C = a.coef;
+  const bool o2 = lr >= 8;
+  if (q < in.h1) return o2 ? (fold ? C + lay.C1D() : nullptr) : C + lay.C1();
+  q -= in.h1;
+  if (q < in.nbas) {
+    const int i = in.i0 + q;
+    if (!o2) return i < in.nv1 ? C + lay.A(i) : nullptr;
+    if (fold) return C + lay.BF(i);
+    return (i >= in.nb && i < in.nv2) ? C + lay.B(i) : nullptr;
+  }
+  return o2 ? C + lay.C2() : nullptr;
+}
+
+template <bool FOLD>
+__global__ __launch_bounds__(256) void update_mfma8(UpdateArgs<double> a, const Ctl* __restrict__ ctl,
+                                                    int obey_stop) {
+  if (obey_stop && ctl && ctl->stop) return;
+  int nv1 = a.nv1, nb = a.nv2_begin, nv2 = a.nv2;
+  if (a.nvp) {
+    nv1 = a.nvp[0];
+    nb = a.nvp[1];
+    nv2 = a.nvp[2];
+    if (nv1 < 0) return;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  if (row0 >= a.n) return;
+  const int lr = lane & 15, lk = lane >> 4;
+  const bool rowv = row0 + lr < a.n;
+  const int64_t arow = rowv ? row0 + lr : a.n - 1;
+  const int nvmax = nv1 > nv2 ? nv1 : nv2;
+  InputSeq<double> in;
+  in.in1 = a.in1;
+  in.in2 = a.in2;
+  in.V = a.V;
+  in.off = arow * 8;
+  in.bstride = a.n * 8;
+  in.h1 = a.in1 ? 1 : 0;
+  in.i0 = nv1 > 0 ? 0 : nb;
+  if (FOLD && nv1 > 0) in.i0 = 0;
+  in.nbas = nvmax > in.i0 ? nvmax - in.i0 : 0;
+  in.nv1 = nv1;
+  in.nb = nb;
+  in.nv2 = nv2;
+  const int nin = in.h1 + in.nbas + (a.in2 ? 1 : 0);
+  const int col = lr & 7;
+  ud4 acc = {0.0, 0.0, 0.0, 0.0};
+  constexpr int U = 4;
+  for (int q0 = 0; q0 < nin; q0 += U) {
+    double av[U][2], bv[U][2];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool qv = q0 + u < nin;
+      const int q = qv ? q0 + u : nin - 1;
+      const double* x = in.ptr(q);
+      const double* c = mf_coef(a, in, q, lr, FOLD);
+      const bool cv = qv && c != nullptr;
+      const double* cc = c ? c : a.coef;
+      // padded rows / inputs and absent coefficient blocks contribute exact zeros
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double xv = x[4 * h + lk];
+        const double cvv = cc[(4 * h + lk) * 8 + col];
+        av[u][h] = (rowv && qv) ? xv : 0.0;
+        bv[u][h] = cv ? cvv : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][h], bv[u][h], acc, 0, 0, 0);
+  }
+  const bool w2 = a.out2 && (a.in2 || nv2 > nb);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = row0 + 4 * r + lk;
+    if (row >= a.n) continue;
+    if (lr < 8) {
+      if (a.out1) a.out1[row * 8 + col] = acc[r];
+    } else if (w2) {
+      a.out2[row * 8 + col] = acc[r];
+    }
+  }
+}
+
 template <typename T, int S>
 void launch_s(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey) {
   const int64_t blocks = (a.n + 255) / 256;
   // coefficients in LDS for s <= 8 (at most (3 + 2 (m+1)) s^2 elements, 34 KiB
   // for s = 8, m = 30); larger s reads them through the scalar cache
-  const size_t coef_bytes = (size_t)a.lay.total() * sizeof(T);
+  if constexpr (sizeof(T) == sizeof(double) && S == 8) {
+    if (a.s == 8) {
+      const int64_t blocks4 = (a.n + 63) / 64;
+      if (a.has_D)
+        update_mfma8<true><<<dim3((unsigned)blocks4), dim3(256), 0, st>>>(a, ctl, obey ? 1 : 0);
+      else
+        update_mfma8<false><<<dim3((unsigned)blocks4), dim3(256), 0, st>>>(a, ctl, obey ? 1 : 0);
+      return;
+    }
+  }
+  // LDS staging covers the coefficients up to D (the folded ones are not read here)
+  const size_t coef_bytes = (size_t)(a.lay.D() + a.s * a.s) * sizeof(T);
   const bool lds = S <= 8 && coef_bytes <= 64 * 1024;
   if (a.s == S) {
     if (lds)

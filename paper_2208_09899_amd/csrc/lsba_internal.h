@@ -92,7 +92,10 @@ struct Dense {
 //   out1 = in1 * C1 + sum_{i < nv1} V_i * A_i
 //   out2 = in2 * C2 + sum_{nv2_begin <= i < nv2} V_i * B_i + out1 * D
 // Every matrix is s x s row-major (entry (t, c) multiplies input column t
-// into output column c).  Offsets (in elements) for block size s, mmax:
+// into output column c).  With D present the same out2 is also
+//   in2 * C2 + in1 * (C1 D) + sum_i V_i * (B_i + A_i D)      (BF(i), C1D()),
+// the form the matrix-core update uses (one product with all inputs).
+// Offsets (in elements) for block size s, mmax:
 struct CoefLayout {
   int s, nvmax;
   __host__ __device__ int C1() const { return 0; }
@@ -100,7 +103,9 @@ struct CoefLayout {
   __host__ __device__ int C2() const { return s * s * (1 + nvmax); }
   __host__ __device__ int B(int i) const { return s * s * (2 + nvmax + i); }
   __host__ __device__ int D() const { return s * s * (2 + 2 * nvmax); }
-  __host__ __device__ int total() const { return s * s * (3 + 2 * nvmax); }
+  __host__ __device__ int BF(int i) const { return s * s * (3 + 2 * nvmax + i); }
+  __host__ __device__ int C1D() const { return s * s * (3 + 3 * nvmax); }
+  __host__ __device__ int total() const { return s * s * (4 + 3 * nvmax); }
 };
 
 // Kernel classes for the device-time statistics (values of lsba_kernel_kind).

@@ -444,6 +444,31 @@ __device__ void set_coef_identity(const Dense& d, int off) {
   bar();
 }
 
+// The folded form of an update with a D term: BF(i) = [nb <= i < nv2] B_i +
+// [i < nv1] A_i D for i < max(nv1, nv2), and C1D = C1 D.  Reads coefficients
+// this workgroup wrote (call after a barrier); ends with a barrier.
+__device__ __forceinline__ void fold_coef(const Dense& d, int nv1, int nb, int nv2) {
+  const int s = d.s, ss = s * s;
+  CoefLayout lay{s, d.mmax + 1};
+  double* c = d.coef64;
+  const double* D = c + lay.D();
+  const int nvm = nv1 > nv2 ? nv1 : nv2;
+  for (int e = threadIdx.x; e < (nvm + 1) * ss; e += NT) {
+    const int blk = e / ss, f = e % ss, i = f / s, j = f % s;
+    if (blk < nvm) {
+      double acc = (blk >= nb && blk < nv2) ? c[lay.B(blk) + f] : 0.0;
+      if (blk < nv1)
+        for (int t = 0; t < s; ++t) acc = fma(c[lay.A(blk) + i * s + t], D[t * s + j], acc);
+      c[lay.BF(blk) + f] = acc;
+    } else {
+      double acc = 0.0;
+      for (int t = 0; t < s; ++t) acc = fma(c[lay.C1() + i * s + t], D[t * s + j], acc);
+      c[lay.C1D() + f] = acc;
+    }
+  }
+  bar();
+}
+
 // Mixed form: the block updates read float coefficients.
 __device__ void publish_coef(const Dense& d) {
   if (!d.mixed) return;
