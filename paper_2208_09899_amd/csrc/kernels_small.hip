@@ -308,12 +308,35 @@ __global__ __launch_bounds__(NT) void small_core_kernel(Dense d, int k, int m, i
       Pn[e] = acc;
     }
     bar();
-    // D = -P R^{-1}
+    // D = -P R^{-1};  W = R^{-1} P R^{-1}
     rows_x_small(s, s, Pn, s, Ri, -1.0, coef + lay.D(), s);
     for (int e = threadIdx.x; e < ss; e += NT) d.PS[(int64_t)k * ss + e] = Pn[e];
+    for (int e = threadIdx.x; e < ss; e += NT) {
+      const int i = e / s, c = e % s;
+      double acc = 0.0;
+      for (int t = 0; t < s; ++t) {
+        double pr = 0.0;
+        for (int u = 0; u < s; ++u) pr = fma(Pn[t * s + u], Ri[u * s + c], pr);
+        acc = fma(Ri[i * s + t], pr, acc);
+      }
+      R[e] = acc;   // R is dead after R^{-1}; W lives there
+    }
+    bar();
+    // folded form: B_i + A_i D = -Z_i R^{-1} + Y_i W,  C1 D = -W
+    for (int e = threadIdx.x; e < r0 * s; e += NT) {
+      const int i = e / s, c = e % s;
+      const double* y = Gp + (int64_t)i * ldg;
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll 8
+      for (int t = 0; t < s; ++t) {
+        a0 = fma(-y[s + t], Ri[t * s + c], a0);
+        a1 = fma(y[t], R[t * s + c], a1);
+      }
+      coef[lay.BF(0) + e] = a0 + a1;
+    }
+    for (int e = threadIdx.x; e < ss; e += NT) coef[lay.C1D() + e] = -R[e];
   }
   bar();
-  if (!last) fold_coef(d, k - 1, 0, k - 1);
   publish_coef(d);
 }
 
@@ -497,8 +520,19 @@ __global__ __launch_bounds__(NT) void small_cwy_kernel(Dense d, int k, int force
   for (int e = threadIdx.x; e < ks * s; e += NT) {
     const int i = e / s, c = e % s;
     d.H[(int64_t)i * ld + (k - 1) * s + c] = Hc[e];
-    if (i < r0) coef[lay.B(0) + e] = -Hc[e];
-    else coef[lay.D() + e - r0 * s] = -Hc[e];
+    if (i < r0) {
+      coef[lay.B(0) + e] = -Hc[e];
+      coef[lay.BF(0) + e] = -Hc[e];   // folded form: no A blocks (V_k = U R^{-1})
+    } else {
+      coef[lay.D() + e - r0 * s] = -Hc[e];
+    }
+  }
+  // C1 D = -R^{-1} H_{k,k}
+  for (int e = threadIdx.x; e < ss; e += NT) {
+    const int i = e / s, c = e % s;
+    double acc = 0.0;
+    for (int t = 0; t < s; ++t) acc = fma(Ri[i * s + t], Hc[(r0 + t) * s + c], acc);
+    coef[lay.C1D() + e] = -acc;
   }
   for (int e = threadIdx.x; e < r0 * s; e += NT) {
     const int i = e / s, c = e % s;
@@ -506,7 +540,6 @@ __global__ __launch_bounds__(NT) void small_cwy_kernel(Dense d, int k, int force
     d.Tt[(int64_t)(r0 + c) * ld + i] = Tc[e];
   }
   bar();
-  fold_coef(d, 0, 0, k - 1);
   publish_coef(d);
 }
 

@@ -24,7 +24,7 @@ __host__ __device__ inline bool side_fits(int s, int k) {
 // slots (Gram output, R^{-1}, P) and H, J, so it may lag the basis kernels.
 // FIT: all operands in LDS (one batched gather); otherwise they live in
 // global scratch slots that no basis-path kernel uses.
-template <bool FIT>
+template <bool FIT, bool FIN>
 __global__ __launch_bounds__(NT) void small_side_kernel(Dense d, int k, int m) {
   __shared__ double lds[LDS_DBL];
   Ctl* ctl = d.ctl;
@@ -192,7 +192,8 @@ __global__ __launch_bounds__(NT) void small_side_kernel(Dense d, int k, int m) {
     rows_x_small(ks, s, T2, s, Ril, 1.0, d.J, s);
     bar();
   }
-  finalize_column(d, k - 1, FIT ? lds + ks * s : lds, FIT ? LDS_DBL - ks * s : LDS_DBL, col, s);
+  if constexpr (FIN)
+    finalize_column(d, k - 1, FIT ? lds + ks * s : lds, FIT ? LDS_DBL - ks * s : LDS_DBL, col, s);
 }
 
 // Column `col` of H is final: QR update, estimate, convergence test.  Runs
@@ -354,11 +355,16 @@ __global__ __launch_bounds__(NT) void small_loo_kernel(Dense d, int kn) {
     if (tm) tm->end(st, KK_SMALL, 0.0);   \
   } while (0)
 
-void launch_small_side(hipStream_t st, const Dense& d, int k, int m, KTimer* tm) {
-  if (side_fits(d.s, k))
-    SMALL_LAUNCH(small_side_kernel<true><<<1, NT, 0, st>>>(d, k, m));
-  else
-    SMALL_LAUNCH(small_side_kernel<false><<<1, NT, 0, st>>>(d, k, m));
+void launch_small_side(hipStream_t st, const Dense& d, int k, int m, bool with_finalize,
+                       KTimer* tm) {
+  const bool fit = side_fits(d.s, k);
+  if (with_finalize) {
+    if (fit) SMALL_LAUNCH(small_side_kernel<true, true><<<1, NT, 0, st>>>(d, k, m));
+    else SMALL_LAUNCH(small_side_kernel<false, true><<<1, NT, 0, st>>>(d, k, m));
+  } else {
+    if (fit) SMALL_LAUNCH(small_side_kernel<true, false><<<1, NT, 0, st>>>(d, k, m));
+    else SMALL_LAUNCH(small_side_kernel<false, false><<<1, NT, 0, st>>>(d, k, m));
+  }
 }
 void launch_small_finalize(hipStream_t st, const Dense& d, int col, KTimer* tm) {
   SMALL_LAUNCH(small_finalize_kernel<<<1, NT, 0, st>>>(d, col));

@@ -49,6 +49,7 @@ struct lsba_context {
   hipEvent_t ev_done = nullptr;   // end of the queued cycle (no timing)
   EventTimer* timer = nullptr;   // non-null while kernel timing is enabled
   hipStream_t side = nullptr;    // second stream: per-column QR updates / convergence tests
+  hipStream_t side2 = nullptr;   // third stream: Alg. 7's QR updates, behind its H / J work
   std::vector<hipEvent_t> evs;   // ordering events between the two streams
   bool async_alloc = false;      // serving slots: stream-ordered allocations on `stream`
 };
@@ -501,14 +502,30 @@ struct CycleRunner {
     };
     std::vector<SideJob> pending;
     constexpr int kSideBatch = 4;
+    // Alg. 7: the H column / J recurrence (a chain over the steps) runs on
+    // `side`, the QR update / convergence test of each finished column on
+    // `side2`, one batch behind, so the two chains overlap.
+    hipStream_t side2 = c->side2;
     auto flush_side = [&]() {
       if (pending.empty()) return;
       hipEvent_t e = event();
       HIPCHK(hipEventRecord(e, st));
       HIPCHK(hipStreamWaitEvent(side, e, 0));
+      bool any_side = false;
       for (const SideJob& j : pending) {
-        if (j.kind == 0) launch_small_finalize(side, d, j.arg, tm);
-        else launch_small_side(side, d, j.arg, j.mcur, tm);
+        if (j.kind == 0) {
+          launch_small_finalize(side, d, j.arg, tm);
+        } else {
+          launch_small_side(side, d, j.arg, j.mcur, false, tm);
+          any_side = true;
+        }
+      }
+      if (any_side) {
+        hipEvent_t e2 = event();
+        HIPCHK(hipEventRecord(e2, side));
+        HIPCHK(hipStreamWaitEvent(side2, e2, 0));
+        for (const SideJob& j : pending)
+          if (j.kind == 1) launch_small_finalize(side2, d, j.arg - 1, tm);
       }
       pending.clear();
     };
@@ -636,12 +653,15 @@ struct CycleRunner {
         }
       }
     }
-    // join the side stream, then end the cycle
+    // join the side streams, then end the cycle
     flush_side();
     {
       hipEvent_t e = event();
       HIPCHK(hipEventRecord(e, side));
       HIPCHK(hipStreamWaitEvent(st, e, 0));
+      hipEvent_t e2 = event();
+      HIPCHK(hipEventRecord(e2, side2));
+      HIPCHK(hipStreamWaitEvent(st, e2, 0));
     }
     tag(1 << 30, 0);
     launch_small_cycle_end(st, d, tm);
@@ -998,6 +1018,7 @@ lsba_status lsba_context_create(int device, void* hip_stream, lsba_context** out
       c->own_stream = true;
     }
     HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking));
     HIPCHK(hipHostMalloc((void**)&c->ctl_host, sizeof(Ctl), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&c->hist_host, sizeof(double) * 2 * (kMaxM + 2),
                          hipHostMallocDefault));
@@ -1033,6 +1054,10 @@ void lsba_context_destroy(lsba_context* c) {
   if (c->side) {
     (void)hipStreamSynchronize(c->side);
     (void)hipStreamDestroy(c->side);
+  }
+  if (c->side2) {
+    (void)hipStreamSynchronize(c->side2);
+    (void)hipStreamDestroy(c->side2);
   }
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
