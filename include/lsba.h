@@ -152,6 +152,17 @@ lsba_status lsba_context_set_timing(lsba_context* ctx, uint32_t kind_mask);
 lsba_status lsba_context_kernel_stats(const lsba_context* ctx, int32_t kind, int64_t* launches,
                                       double* total_ms, double* total_bytes);
 
+/* Cycle replay.  A cycle's launch sequence depends only on host values fixed
+ * for a solve (buffer and operator pointers, sizes, method, skeleton, muscle,
+ * restart length).  With enable = 1 it is captured into a hipGraph on first
+ * use and replayed with one launch per cycle; the context keeps up to 8 such
+ * graphs, keyed by those values, and drops them all when a cached buffer is
+ * freed or this setting changes.  enable = 0 (the default) launches every
+ * kernel individually, which on ROCm keeps the three streams' kernels
+ * overlapping best.  Results are bitwise the same either way; while kernel
+ * timing is enabled cycles are always launched individually. */
+lsba_status lsba_context_set_graphs(lsba_context* ctx, int enable);
+
 /* Copy a CSR matrix (layout above) into device memory owned by the operator.
  * Validates the row pointer (monotone, row_ptr[0] = 0, row_ptr[n] = nnz) and
  * the column range; an invalid matrix gives LSBA_ERR_ARG. */

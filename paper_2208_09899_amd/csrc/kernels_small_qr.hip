@@ -7,24 +7,14 @@ namespace lsba {
 
 namespace {
 
-// LDS layout of small_side when everything fits (in the order the sources are
-// gathered): the column [J; R] (k s x s), Y, Z ((k-1) s x s each), P, R^{-1},
-// T2 (k s x s), then at least one column block of H staged per chunk.
-__host__ __device__ inline bool side_fits(int s, int k) {
-  const int ss = s * s, r0 = (k - 1) * s, ks = k * s;
-  const int fixed = ks * s + 2 * r0 * s + 2 * ss + ks * s;
-  const int fin = 16 * ss;   // finalize_lds_min
-  return fixed + r0 * s <= LDS_DBL && ks * s + fin <= LDS_DBL;
-}
-
 // Alg. 7 off the basis path, after loop step k >= 2 (queued on a second
-// stream behind small_core of the same step): H_{1:k-1,k-1} = J + Y, for
-// k <= m the J recurrence J = ([Z; P] - H_{1:k,1:k-1} Y) R^{-1}, then column
-// k-1 is final and goes through finalize_column.  It reads only this step's
-// slots (Gram output, R^{-1}, P) and H, J, so it may lag the basis kernels.
-// FIT: all operands in LDS (one batched gather); otherwise they live in
-// global scratch slots that no basis-path kernel uses.
-template <bool FIT, bool FIN>
+// stream behind small_core of the same step): H_{1:k-1,k-1} = J + Y and, for
+// k <= m, the J recurrence J = ([Z; P] - H_{1:k,1:k-1} Y) R^{-1}.  Every
+// quantity here is row-local (row a of the new H column, of T2 and of J
+// depends on row a of J, Y, Z, H only), so workgroup rb takes block row rb of
+// the k block rows and the kernel runs k workgroups side by side.  It reads
+// only this step's slots (Gram output, R^{-1}, P) and H, J, so it may lag the
+// basis kernels.
 __global__ __launch_bounds__(NT) void small_side_kernel(Dense d, int k, int m) {
   __shared__ double lds[LDS_DBL];
   Ctl* ctl = d.ctl;
@@ -36,164 +26,123 @@ __global__ __launch_bounds__(NT) void small_side_kernel(Dense d, int k, int m) {
   const int s = d.s, ld = d.ldh, ss = s * s;
   const bool last = (k == m + 1);
   const int ldg = last ? s : 2 * s;
-  const int r0 = (k - 1) * s, ks = k * s;
-  const int c1 = (k - 2) * s;   // first column of block column k-1
-  const double* Gk = d.G + (int64_t)k * d.gstride;
-  const Scr sc = make_scr(d);
-  double* col;
-  double* Yl;
-  double* Zl;
-  double* Pl;
-  double* Ril;
-  double* T2;
-  double* Hs;
-  int hcap;
-  if constexpr (FIT) {
-    col = lds;
-    Yl = col + ks * s;
-    Zl = Yl + r0 * s;
-    Pl = Zl + r0 * s;
-    Ril = Pl + ss;
-    T2 = Ril + ss;
-    Hs = T2 + ks * s;
-    hcap = LDS_DBL - (int)(Hs - lds);
+  const int r0 = (k - 1) * s, c1 = (k - 2) * s;
+  const int rb = blockIdx.x, a0 = rb * s;
+  const double* Gk = d.G + (int64_t)k * d.gstride;   // [Y Z]: row t holds Y(t, :), Z(t, :)
+  const int tid = threadIdx.x;
+  // block rb of the new column: J + Y above block row k, R = H_{k,k-1} in it
+  double* hc = lds;            // ss
+  double* t2 = hc + ss;        // ss
+  double* stage = t2 + ss;     // chunks of H rows (s x ck) and Y rows (ck x s); R^{-1}
+  for (int e = tid; e < ss; e += NT) {
+    const int i = e / s, c = e % s, a = a0 + i;
+    double v;
+    if (rb < k - 1) {
+      v = d.J[(int64_t)a * s + c] + Gk[(int64_t)a * ldg + c];
+      d.H[(int64_t)a * ld + c1 + c] = v;
+    } else {
+      v = d.H[(int64_t)(r0 + i) * ld + c1 + c];
+    }
+    hc[e] = v;
+  }
+  if (last) return;
+  // T2 rows a0 .. a0 + s: sum over the band t in [lo, r0) of H(a, t) Y(t, :);
+  // block row rb of H has nonzeros from column block rb - 1 on, and its
+  // entries in the last column block are hc.
+  const int lo = (rb > 1 ? rb - 1 : 0) * s;
+  const int ck = (LDS_DBL - 2 * ss) / (2 * s);
+  double* hs = stage;            // s x ck
+  double* ys = stage + s * ck;   // ck x s
+  // outputs of this thread: e = tid % ss (+ q NT for s^2 > NT); split of the
+  // t range over kp parts when s^2 < NT
+  const int kp = ss >= NT ? 1 : NT / ss;
+  const int part = ss >= NT ? 0 : tid / ss;
+  const bool active = part < kp;
+  constexpr int kQ = kMaxS * kMaxS / NT;
+  double acc[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) acc[q] = 0.0;
+  for (int t0 = lo; t0 < r0; t0 += ck) {
+    const int w = (r0 - t0) < ck ? (r0 - t0) : ck;
+    bar();   // hc written / previous chunk consumed
+    const int nh = s * w;
+    for (int base = tid; base < 2 * nh; base += NT * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int e = base + u * NT;
+        e = e < 2 * nh ? e : 2 * nh - 1;
+        if (e < nh) {
+          const int i = e / w, t = t0 + e % w;
+          v[u] = t < c1 ? d.H[(int64_t)(a0 + i) * ld + t] : hc[i * s + (t - c1)];
+        } else {
+          const int f = e - nh, t = t0 + f / s;
+          v[u] = Gk[(int64_t)t * ldg + f % s];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * NT;
+        if (e < nh) hs[e] = v[u];
+        else if (e < 2 * nh) ys[e - nh] = v[u];
+      }
+    }
+    bar();
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const int e = (ss >= NT ? tid + q * NT : tid % ss);
+        if (e < ss && (q == 0 || ss >= NT)) {
+          const int i = e / s, c = e % s;
+          const double* hr = hs + i * w;
+          double x0 = 0.0, x1 = 0.0;
+          int tt = part;
+          for (; tt + kp < w; tt += 2 * kp) {
+            x0 = fma(hr[tt], ys[tt * s + c], x0);
+            x1 = fma(hr[tt + kp], ys[(tt + kp) * s + c], x1);
+          }
+          if (tt < w) x0 = fma(hr[tt], ys[tt * s + c], x0);
+          acc[q] += x0 + x1;
+        }
+      }
+    }
+  }
+  bar();
+  // T2 = [Z; P] - (sum over the parts), in a fixed order
+  if (kp > 1) {
+    if (active) stage[part * ss + tid % ss] = acc[0];
+    bar();
+    for (int e = tid; e < ss; e += NT) {
+      double sum = 0.0;
+      for (int p = 0; p < kp; ++p) sum += stage[p * ss + e];
+      const int i = e / s, c = e % s;
+      const double zp = rb < k - 1 ? Gk[(int64_t)(a0 + i) * ldg + s + c]
+                                   : d.PS[(int64_t)k * ss + e];
+      t2[e] = zp - sum;
+    }
   } else {
-    col = sc.bg(7);
-    Yl = sc.bg(4);
-    Zl = sc.bg(5);
-    T2 = sc.bg(6);
-    Pl = sc.bg(4) + (int64_t)d.mmax * ss;
-    Ril = Pl + ss;
-    Hs = lds;
-    hcap = LDS_DBL;
-  }
-  // gather J, R = H_{k,k-1}, Y, Z, P, R^{-1}: element e of the sequence
-  const int nJ = r0 * s, nY = r0 * s, nZ = last ? 0 : r0 * s, nP = last ? 0 : ss;
-  const int eR = nJ, eY = eR + ss, eZ = eY + nY, eP = eZ + nZ, eRi = eP + nP;
-  const int tot = eRi + nP;
-  auto src = [&](int e) -> const double* {
-    if (e < eR) return d.J + e;
-    if (e < eY) return d.H + (int64_t)(r0 + (e - eR) / s) * ld + c1 + (e - eR) % s;
-    if (e < eZ) return Gk + (int64_t)((e - eY) / s) * ldg + (e - eY) % s;
-    if (e < eP) return Gk + (int64_t)((e - eZ) / s) * ldg + s + (e - eZ) % s;
-    if (e < eRi) return d.PS + (int64_t)k * ss + (e - eP);
-    return d.RiS + (int64_t)k * ss + (e - eRi);
-  };
-  auto dst = [&](int e) -> double* {
-    if constexpr (FIT) {
-      // col, Yl, Zl, Pl, Ril are contiguous in gather order; with no Z the
-      // P and R^{-1} slots are skipped (unused on the last step)
-      return lds + e;
-    } else {
-      if (e < eY) return col + e;
-      if (e < eZ) return Yl + (e - eY);
-      if (e < eP) return Zl + (e - eZ);
-      if (e < eRi) return Pl + (e - eP);
-      return Ril + (e - eRi);
-    }
-  };
-  for (int base = threadIdx.x; base < tot; base += NT * 16) {
-    double v[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = base + u * NT;
-      v[u] = *src(e < tot ? e : tot - 1);
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = base + u * NT;
-      if (e < tot) *dst(e) = v[u];
+    for (int q = 0; q < kQ; ++q) {
+      const int e = tid + q * NT;
+      if (e < ss) {
+        const int i = e / s, c = e % s;
+        const double zp = rb < k - 1 ? Gk[(int64_t)(a0 + i) * ldg + s + c]
+                                     : d.PS[(int64_t)k * ss + e];
+        t2[e] = zp - acc[q];
+      }
     }
   }
   bar();
-  // H_{1:k-1,k-1} = J + Y
-  for (int e = threadIdx.x; e < r0 * s; e += NT) {
-    const double v = col[e] + Yl[e];
-    col[e] = v;
-    d.H[(int64_t)(e / s) * ld + c1 + (e % s)] = v;
-  }
+  // J rows = T2 R^{-1}
+  double* ri = stage;
+  for (int e = tid; e < ss; e += NT) ri[e] = d.RiS[(int64_t)k * ss + e];
   bar();
-  if (!last) {
-    // T2 = [Z; P] - H_{1:k,1:k-1} Y.  First the last column block (in col:
-    // J + Y above, R below), then H_{1:k-1,1:k-2} from global memory, staged
-    // in LDS a few column blocks at a time; row block rb has nonzeros from
-    // column block rb - 1 on.
-    const double* Ylast = Yl + (int64_t)c1 * s;
-    for (int e = threadIdx.x; e < ks * s; e += NT) {
-      const int a = e / s, c = e % s;
-      double acc = a < r0 ? Zl[e] : Pl[e - r0 * s];
-#pragma unroll 8
-      for (int t = 0; t < s; ++t) acc = fma(-col[a * s + t], Ylast[t * s + c], acc);
-      T2[e] = acc;
-    }
-    const int nbc = k - 2;   // column blocks of the global part
-    if constexpr (FIT) {
-      for (int cb0 = 0; cb0 < nbc;) {
-        int cb1 = cb0 + 1;
-        auto rows_of = [&](int cbe) { return (cbe + 1) * s < r0 ? (cbe + 1) * s : r0; };
-        while (cb1 < nbc && rows_of(cb1 + 1) * (cb1 + 1 - cb0) * s <= hcap) ++cb1;
-        const int nrows = rows_of(cb1), w = (cb1 - cb0) * s, t0 = cb0 * s;
-        const int ntot = nrows * w;
-        bar();   // previous chunk consumed (and T2 initialised)
-        for (int base = threadIdx.x; base < ntot; base += NT * 16) {
-          double v[16];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            int e = base + u * NT;
-            e = e < ntot ? e : ntot - 1;
-            const int a = e / w, t = t0 + e % w;
-            v[u] = d.H[(int64_t)a * ld + t];
-            const int lo = (a / s > 1 ? a / s - 1 : 0) * s;
-            v[u] = t >= lo ? v[u] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const int e = base + u * NT;
-            if (e < ntot) Hs[e] = v[u];
-          }
-        }
-        bar();
-        for (int e = threadIdx.x; e < nrows * s; e += NT) {
-          const int a = e / s, c = e % s;
-          const double* hr = Hs + a * w;
-          const double* yc = Yl + (int64_t)t0 * s + c;
-          double a0 = 0.0, a1 = 0.0;
-          int t = 0;
-#pragma unroll 4
-          for (; t + 1 < w; t += 2) {
-            a0 = fma(hr[t], yc[t * s], a0);
-            a1 = fma(hr[t + 1], yc[(t + 1) * s], a1);
-          }
-          if (t < w) a0 = fma(hr[t], yc[t * s], a0);
-          T2[e] -= a0 + a1;
-        }
-        cb0 = cb1;
-      }
-    } else {
-      // operands in global memory: row a against the columns of its band
-      bar();
-      for (int e = threadIdx.x; e < r0 * s; e += NT) {
-        const int a = e / s, c = e % s;
-        const int lo = (a / s > 1 ? a / s - 1 : 0) * s;
-        const double* hr = d.H + (int64_t)a * ld;
-        double a0 = 0.0, a1 = 0.0;
-        int t = lo;
-#pragma unroll 4
-        for (; t + 1 < c1; t += 2) {
-          a0 = fma(hr[t], Yl[t * s + c], a0);
-          a1 = fma(hr[t + 1], Yl[(t + 1) * s + c], a1);
-        }
-        if (t < c1) a0 = fma(hr[t], Yl[t * s + c], a0);
-        T2[e] -= a0 + a1;
-      }
-    }
-    bar();
-    // J = T2 R^{-1}
-    rows_x_small(ks, s, T2, s, Ril, 1.0, d.J, s);
-    bar();
+  for (int e = tid; e < ss; e += NT) {
+    const int i = e / s, c = e % s;
+    double x = 0.0;
+    for (int u = 0; u < s; ++u) x = fma(t2[i * s + u], ri[u * s + c], x);
+    d.J[(int64_t)(a0 + i) * s + c] = x;
   }
-  if constexpr (FIN)
-    finalize_column(d, k - 1, FIT ? lds + ks * s : lds, FIT ? LDS_DBL - ks * s : LDS_DBL, col, s);
 }
 
 // Column `col` of H is final: QR update, estimate, convergence test.  Runs
@@ -210,9 +159,166 @@ __global__ __launch_bounds__(NT) void small_finalize_kernel(Dense d, int col) {
   finalize_column(d, col, lds, LDS_DBL, d.H + (int64_t)(col - 1) * d.s, d.ldh);
 }
 
+// Register-resident back substitution / M chain of small_cycle_end: used
+// when the j s x s block coefficient vector fits kCeRegs doubles per thread.
+constexpr int kCeRegs = 8;
+__host__ __device__ inline bool cycle_end_fast(int s, int j) { return j * s * s <= kCeRegs * NT; }
+
+// Xi = R^{-1} g by block back substitution, right-looking: after block b is
+// solved, the rows above it take their update from column block b at once,
+// each thread updating the entries of Xi it owns (in registers); the column
+// block for the next step is fetched while this one is applied.  The
+// diagonal blocks are inverted up front, all of them side by side.  Writes Xi
+// to the A coefficients and returns (in LDS, at xlast) its last block.
+// GMRES, not final: M = Q_1 ... Q_{j-1} E_j S with S = D^{-T} (H_{j+1,j}^T
+// H_{j+1,j}); Q_i touches block rows i, i + 1 only and block row i is still
+// zero when it applies, so the chain carries one s x s block w:
+// M_{i+1} = Q_i[s:2s, s:2s]^T w and w <- Q_i[s:2s, 0:s]^T w (Q_i^T stored).
+__device__ void cycle_end_regs(const Dense& d, int j, bool want_m, double* lds) {
+  const int s = d.s, ld = d.ldh, ss = s * s, js = j * s, n = js * s;
+  CoefLayout lay{s, d.mmax + 1};
+  const int tid = threadIdx.x;
+  double* Dg = lds;                    // j x ss   diagonal blocks of R
+  double* Ri = Dg + j * ss;            // j x ss   their inverses
+  double* rc0 = Ri + j * ss;           // js x s   column block of R above the diagonal
+  double* rc1 = rc0 + n;               // js x s   (double buffer)
+  double* xb = rc1 + n;                // ss       solved block
+  double* xn = xb + ss;                // ss       next block's right-hand side
+  double* Qs = xn + ss;                // (j - 1) x (s x 2s)   rows s..2s of each Q_i^T
+  double* w0 = Qs + (j - 1) * 2 * ss;  // ss
+  double* w1 = w0 + ss;                // ss
+  double* Dt = w1 + ss;                // ss
+  double xr[kCeRegs];
+#pragma unroll
+  for (int q = 0; q < kCeRegs; ++q) {
+    const int e = tid + q * NT;
+    xr[q] = e < n ? d.g[e] : 0.0;
+  }
+  for (int e = tid; e < j * ss; e += NT) {
+    const int b = e / ss, f = e % ss;
+    Dg[e] = d.Rf[(int64_t)(b * s + f / s) * ld + b * s + f % s];
+  }
+  {
+    const int nr = (j - 1) * s * s;   // column block j, rows above the diagonal
+    for (int e = tid; e < nr; e += NT)
+      rc0[e] = d.Rf[(int64_t)(e / s) * ld + (j - 1) * s + e % s];
+  }
+  if (want_m)
+    for (int e = tid; e < (j - 1) * 2 * ss; e += NT) {
+      const int i = e / (2 * ss), f = e % (2 * ss);
+      Qs[e] = d.Qt[(int64_t)i * 4 * ss + 2 * ss + f];
+    }
+  bar();
+  // inverses of the diagonal blocks: thread (b, c) solves R_bb x = e_c
+  if (tid < j * s) {
+    const int b = tid / s, c = tid % s;
+    const double* R = Dg + b * ss;
+    double* X = Ri + b * ss;
+    for (int r = s - 1; r >= 0; --r) {
+      double x = (r == c) ? 1.0 : 0.0;
+      for (int t = r + 1; t < s; ++t) x = fma(-R[r * s + t], X[t * s + c], x);
+      X[r * s + c] = r > c ? 0.0 : x / R[r * s + r];
+    }
+  }
+  bar();
+  // last block: FOM's comes with the column's test, GMRES solves R_jj x = g_j
+  double* coefA = d.coef64 + lay.A(0);
+  for (int e = tid; e < ss; e += NT) {
+    const int r = e / s, c = e % s;
+    double x;
+    if (d.method == LSBA_FOM) {
+      x = d.ylast[e];
+    } else {
+      const double* R = Ri + (j - 1) * ss;
+      const double* g = d.g + (int64_t)(j - 1) * ss;
+      x = 0.0;
+      for (int t = 0; t < s; ++t) x = fma(R[r * s + t], g[t * s + c], x);
+    }
+    xb[e] = x;
+    coefA[(int64_t)(j - 1) * ss + e] = x;
+  }
+  bar();
+  double* cur = rc0;
+  double* nxt = rc1;
+  for (int b = j; b >= 2; --b) {
+    // rows above block b take column block b; fetch column block b - 1
+    const int top = (b - 1) * s;     // rows updated: a < top
+    const int nn = (b - 2) * s * s;  // column block b - 1, rows above its diagonal
+    double pf[kCeRegs];
+#pragma unroll
+    for (int q = 0; q < kCeRegs; ++q) {
+      const int e = tid + q * NT;
+      pf[q] = e < nn ? d.Rf[(int64_t)(e / s) * ld + (b - 2) * s + e % s] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kCeRegs; ++q) {
+      const int e = tid + q * NT;
+      const int a = e / s, c = e % s;
+      if (a < top) {
+        double x = xr[q];
+        for (int t = 0; t < s; ++t) x = fma(-cur[a * s + t], xb[t * s + c], x);
+        xr[q] = x;
+        if (a >= top - s) xn[(a - (top - s)) * s + c] = x;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kCeRegs; ++q) {
+      const int e = tid + q * NT;
+      if (e < nn) nxt[e] = pf[q];
+    }
+    bar();
+    // block b - 1 = R_{b-1,b-1}^{-1} (its updated right-hand side)
+    for (int e = tid; e < ss; e += NT) {
+      const int r = e / s, c = e % s;
+      const double* R = Ri + (b - 2) * ss;
+      double x = 0.0;
+      for (int t = 0; t < s; ++t) x = fma(R[r * s + t], xn[t * s + c], x);
+      xb[e] = x;
+      coefA[(int64_t)(b - 2) * ss + e] = x;
+    }
+    bar();
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  if (!want_m) return;
+  // S = D^{-T} (H_{j+1,j}^T H_{j+1,j})
+  const double* Hsub = d.H + (int64_t)js * ld + (j - 1) * s;
+  for (int e = tid; e < ss; e += NT) {
+    const int r = e / s, c = e % s;
+    double x = 0.0;
+    for (int t = 0; t < s; ++t) x = fma(Hsub[(int64_t)t * ld + r], Hsub[(int64_t)t * ld + c], x);
+    w0[e] = x;
+    Dt[e] = d.Dlast[c * s + r];
+  }
+  bar();
+  lu_solve(Dt, w0, s, s);
+  bar();
+  double* coefB = d.coef64 + lay.B(0);
+  double* wc = w0;
+  double* wn = w1;
+  for (int i = j - 1; i >= 1; --i) {
+    const double* Q = Qs + (i - 1) * 2 * ss;   // Q[t * 2s + r] = (Q_i^T)[s + t][r]
+    for (int e = tid; e < 2 * ss; e += NT) {
+      const int r = e / s, c = e % s;
+      double x = 0.0;
+      for (int t = 0; t < s; ++t) x = fma(Q[t * 2 * s + r], wc[t * s + c], x);
+      if (r < s) wn[r * s + c] = x;
+      else coefB[(int64_t)i * ss + (r - s) * s + c] = x;
+    }
+    bar();
+    double* t = wc;
+    wc = wn;
+    wn = t;
+  }
+  for (int e = tid; e < ss; e += NT) coefB[e] = wc[e];
+  bar();
+}
+
 // End of a cycle: Xi, M, the cospatial factor, the basis-application
 // coefficients and the adaptive restart bookkeeping.
 __global__ __launch_bounds__(NT) void small_cycle_end_kernel(Dense d) {
+  __shared__ double lds[LDS_DBL];
   const Scr sc = make_scr(d);
   Ctl* ctl = d.ctl;
   const int s = d.s, ld = d.ldh, ss = s * s;
@@ -235,32 +341,36 @@ __global__ __launch_bounds__(NT) void small_cycle_end_kernel(Dense d) {
     return;
   }
   const int js = j * s, c0 = (j - 1) * s;
-  double* Xi = d.Xi;
-  // last block of Xi
-  if (d.method == LSBA_FOM) {
-    copy(s, s, d.ylast, s, Xi + (int64_t)c0 * s, s);
-  } else {
-    copy(s, s, d.g + (int64_t)c0 * s, s, Xi + (int64_t)c0 * s, s);
-    tri_solve_up(d.Rf + (int64_t)c0 * ld + c0, ld, s, Xi + (int64_t)c0 * s, s, s);
-  }
-  // block back substitution with the triangular factor
-  for (int b = j - 1; b >= 1; --b) {
-    const int rb = (b - 1) * s;
-    double* xb = Xi + (int64_t)rb * s;
-    copy(s, s, d.g + (int64_t)rb * s, s, xb, s);
-    mm(s, s, js - (rb + s), -1.0, d.Rf + (int64_t)rb * ld + rb + s, ld, false,
-       Xi + (int64_t)(rb + s) * s, s, false, 1.0, xb, s);
-    tri_solve_up(d.Rf + (int64_t)rb * ld + rb, ld, s, xb, s, s);
-  }
   const bool final_ = (status == ST_CONVERGED || status == ST_ITERCAP);
-  // X += V_{1:j} Xi
+  const bool want_m = !final_ && d.method == LSBA_GMRES;
+  // X += V_{1:j} Xi (C1 = I, A = Xi)
   set_coef_identity(d, lay.C1());
-  copy(js, s, Xi, s, d.coef64 + lay.A(0), s);
-  const double* Hsub = d.H + (int64_t)js * ld + c0;
-  int nvb = 0, nve = 0;
-  if (!final_) {
-    if (d.method == LSBA_GMRES) {
+  const double* xlast;
+  if (cycle_end_fast(s, j)) {
+    cycle_end_regs(d, j, want_m, lds);
+    xlast = d.coef64 + lay.A(j - 1);
+  } else {
+    double* Xi = d.Xi;
+    // last block of Xi
+    if (d.method == LSBA_FOM) {
+      copy(s, s, d.ylast, s, Xi + (int64_t)c0 * s, s);
+    } else {
+      copy(s, s, d.g + (int64_t)c0 * s, s, Xi + (int64_t)c0 * s, s);
+      tri_solve_up(d.Rf + (int64_t)c0 * ld + c0, ld, s, Xi + (int64_t)c0 * s, s, s);
+    }
+    // block back substitution with the triangular factor
+    for (int b = j - 1; b >= 1; --b) {
+      const int rb = (b - 1) * s;
+      double* xb = Xi + (int64_t)rb * s;
+      copy(s, s, d.g + (int64_t)rb * s, s, xb, s);
+      mm(s, s, js - (rb + s), -1.0, d.Rf + (int64_t)rb * ld + rb + s, ld, false,
+         Xi + (int64_t)(rb + s) * s, s, false, 1.0, xb, s);
+      tri_solve_up(d.Rf + (int64_t)rb * ld + rb, ld, s, xb, s, s);
+    }
+    copy(js, s, Xi, s, d.coef64 + lay.A(0), s);
+    if (want_m) {
       // M = Q_1 ... Q_{j-1} E_j D^{-T} (H_{j+1,j}^T H_{j+1,j})
+      const double* Hsub = d.H + (int64_t)js * ld + c0;
       double* S = sc.sm(2);
       mm(s, s, s, 1.0, Hsub, ld, true, Hsub, ld, false, 0.0, S, s);
       double* Dt = sc.sm(3);
@@ -278,11 +388,13 @@ __global__ __launch_bounds__(NT) void small_cycle_end_kernel(Dense d) {
         copy(2 * s, s, w2, s, Mw, s);
       }
       copy(js, s, d.M, s, d.coef64 + lay.B(0), s);
-      nvb = 0;
-    } else {
-      nvb = j;
     }
-    set_coef(d, lay.B(j), Hsub, ld, -1.0);
+    xlast = Xi + (int64_t)c0 * s;
+  }
+  int nvb = 0, nve = 0;
+  if (!final_) {
+    nvb = d.method == LSBA_GMRES ? 0 : j;
+    set_coef(d, lay.B(j), d.H + (int64_t)js * ld + c0, ld, -1.0);
     nve = j + 1;
   }
   if (threadIdx.x == 0) {
@@ -294,7 +406,7 @@ __global__ __launch_bounds__(NT) void small_cycle_end_kernel(Dense d) {
   }
   bar();
   if (!final_) {
-    copy(s, s, Xi + (int64_t)c0 * s, s, d.C, s);
+    copy(s, s, xlast, s, d.C, s);
     if (threadIdx.x == 0) {
       ctl->status = ST_RUNNING;
       ctl->stop = 0;
@@ -355,16 +467,9 @@ __global__ __launch_bounds__(NT) void small_loo_kernel(Dense d, int kn) {
     if (tm) tm->end(st, KK_SMALL, 0.0);   \
   } while (0)
 
-void launch_small_side(hipStream_t st, const Dense& d, int k, int m, bool with_finalize,
-                       KTimer* tm) {
-  const bool fit = side_fits(d.s, k);
-  if (with_finalize) {
-    if (fit) SMALL_LAUNCH(small_side_kernel<true, true><<<1, NT, 0, st>>>(d, k, m));
-    else SMALL_LAUNCH(small_side_kernel<false, true><<<1, NT, 0, st>>>(d, k, m));
-  } else {
-    if (fit) SMALL_LAUNCH(small_side_kernel<true, false><<<1, NT, 0, st>>>(d, k, m));
-    else SMALL_LAUNCH(small_side_kernel<false, false><<<1, NT, 0, st>>>(d, k, m));
-  }
+void launch_small_side(hipStream_t st, const Dense& d, int k, int m, KTimer* tm) {
+  const int rows = (k == m + 1) ? k - 1 : k;   // the last step only writes the H column
+  SMALL_LAUNCH(small_side_kernel<<<rows, NT, 0, st>>>(d, k, m));
 }
 void launch_small_finalize(hipStream_t st, const Dense& d, int col, KTimer* tm) {
   SMALL_LAUNCH(small_finalize_kernel<<<1, NT, 0, st>>>(d, col));

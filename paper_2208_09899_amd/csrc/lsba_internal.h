@@ -188,11 +188,10 @@ void launch_small_start(hipStream_t st, const Dense& d, int force_flag, KTimer* 
 void launch_small_delayed(hipStream_t st, const Dense& d, int k, int m, int force_flag,
                           KTimer* tm = nullptr);
 void launch_small_finalize(hipStream_t st, const Dense& d, int col, KTimer* tm = nullptr);
-// Alg. 7 off the basis path, after loop step k >= 2: H_{1:k-1,k-1} = J + Y, the
-// J recurrence, then (with_finalize) the QR update / estimate / convergence
-// test of column k-1 (else launch_small_finalize does it, on another stream).
-void launch_small_side(hipStream_t st, const Dense& d, int k, int m, bool with_finalize,
-                       KTimer* tm = nullptr);
+// Alg. 7 off the basis path, after loop step k >= 2: H_{1:k-1,k-1} = J + Y and
+// the J recurrence, one workgroup per block row (the QR update / estimate /
+// convergence test of column k-1 follows with launch_small_finalize).
+void launch_small_side(hipStream_t st, const Dense& d, int k, int m, KTimer* tm = nullptr);
 void launch_small_svl_y(hipStream_t st, const Dense& d, int k, KTimer* tm = nullptr);
 void launch_small_svl_io(hipStream_t st, const Dense& d, int k, int force_flag,
                          KTimer* tm = nullptr);

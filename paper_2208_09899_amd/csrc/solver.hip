@@ -8,7 +8,10 @@
 // kernels test the device control word and return at once after convergence,
 // a Cholesky flag (Sec. 4) or the iteration cap, so the host synchronises
 // only once per cycle, to read the control word and the cycle's residual
-// estimates.
+// estimates.  A cycle's launch sequence depends only on host values fixed for
+// the solve (pointers, sizes, method, restart length), so it can also be
+// captured once into a hipGraph and replayed with one host call per cycle
+// (lsba_context_set_graphs).
 //
 // The mixed form wraps FP32 inner solves (same cycle machinery with float
 // blocks) in FP64 iterative refinement: R = B - A X in FP64, inner solve
@@ -21,6 +24,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lsba_internal.h"
@@ -52,6 +56,16 @@ struct lsba_context {
   hipStream_t side2 = nullptr;   // third stream: Alg. 7's QR updates, behind its H / J work
   std::vector<hipEvent_t> evs;   // ordering events between the two streams
   bool async_alloc = false;      // serving slots: stream-ordered allocations on `stream`
+  // Captured cycles, keyed by every host value their launches read (see
+  // CycleRunner::graph_key); dropped whenever a cached buffer is freed.
+  struct GraphEnt {
+    std::vector<uint8_t> key;
+    hipGraphExec_t ex = nullptr;
+    uint64_t used = 0;
+  };
+  std::vector<GraphEnt> graphs;
+  uint64_t graph_tick = 0;
+  bool graphs_on = false;
 };
 
 
@@ -204,10 +218,43 @@ struct Unsupported {
   std::string msg;
 };
 
+constexpr size_t kMaxGraphs = 8;
+
+// Destroy every captured cycle of a context (their launches may still be in
+// flight on the context's stream, so it is drained first).
+void graphs_clear(lsba_context* c) {
+  if (c->graphs.empty()) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.ex);
+  c->graphs.clear();
+}
+
+hipGraphExec_t graph_find(lsba_context* c, const std::vector<uint8_t>& key) {
+  for (auto& g : c->graphs)
+    if (g.key == key) {
+      g.used = ++c->graph_tick;
+      return g.ex;
+    }
+  return nullptr;
+}
+
+void graph_put(lsba_context* c, std::vector<uint8_t> key, hipGraphExec_t ex) {
+  if (c->graphs.size() >= kMaxGraphs) {
+    auto lru = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                [](const lsba_context::GraphEnt& a,
+                                   const lsba_context::GraphEnt& b) { return a.used < b.used; });
+    if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+    (void)hipGraphExecDestroy(lru->ex);
+    c->graphs.erase(lru);
+  }
+  c->graphs.push_back({std::move(key), ex, ++c->graph_tick});
+}
+
 void* ctx_buf(lsba_context* c, const std::string& name, size_t bytes) {
   auto& b = c->bufs[name];
   if (b.bytes < bytes) {
     if (b.p) {
+      graphs_clear(c);   // captured launches may point into the old buffer
       if (c->async_alloc) HIPCHK(hipFreeAsync(b.p, c->stream));
       else HIPCHK(hipFree(b.p));
     }
@@ -226,6 +273,7 @@ void* ctx_buf(lsba_context* c, const std::string& name, size_t bytes) {
 
 // Release every cached buffer of a context (stream-ordered for serving slots).
 void ctx_release(lsba_context* c) {
+  graphs_clear(c);
   for (auto& kv : c->bufs)
     if (kv.second.p) {
       if (c->async_alloc) (void)hipFreeAsync(kv.second.p, c->stream);
@@ -467,7 +515,73 @@ struct CycleRunner {
     m = p.m;
   }
 
+  // Host values the launches of cycle cyc_ read: workspace and operator
+  // pointers and sizes (the Krylov state holds no padding, so its bytes are
+  // its values), the starting block, X, the restart length, the forced flag.
+  std::vector<uint8_t> graph_key(int cyc_) const {
+    static_assert(std::has_unique_object_representations_v<Krylov<T>>,
+                  "the Krylov state must hold no padding bytes");
+    std::vector<uint8_t> b;
+    auto put = [&](const void* q, size_t nb) {
+      const uint8_t* u = (const uint8_t*)q;
+      b.insert(b.end(), u, u + nb);
+    };
+    const int fk = (p.force_flag_cycle == cyc_) ? p.force_flag_step : -1;
+    const int64_t ints[] = {(int64_t)sizeof(T), op->n, op->nnz, m, fk, p.muscle, p.skeleton,
+                            p.method, rec_loo ? 1 : 0};
+    const void* ptrs[] = {op->rp, op->ci, val, R0, x, c->side, c->side2};
+    put(ints, sizeof(ints));
+    put(ptrs, sizeof(ptrs));
+    put(kp, sizeof(Krylov<T>));
+    return b;
+  }
+
+  // Queue one cycle: replay its captured graph (capturing it on first use),
+  // or launch it kernel by kernel while kernel timing is on; then the
+  // read-back of the control word and the residual estimates.
   void enqueue() {
+    const int cyc_ = ++cyc;
+    hipStream_t st = c->stream;
+    Dense& d = kp->d;
+    if (c->graphs_on && c->timer == nullptr) {
+      std::vector<uint8_t> key = graph_key(cyc_);
+      hipGraphExec_t ex = graph_find(c, key);
+      if (!ex) {
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        hipGraph_t g = nullptr;
+        try {
+          record(cyc_);
+        } catch (...) {
+          (void)hipStreamEndCapture(st, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        HIPCHK(hipStreamEndCapture(st, &g));
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+        graph_put(c, std::move(key), ex);
+      }
+      HIPCHK(hipGraphLaunch(ex, st));
+    } else {
+      record(cyc_);
+    }
+    uapply = upd_args(*kp);
+    uapply.in1 = x;
+    uapply.out1 = x;
+    uapply.out2 = kp->U;
+    uapply.nvp = &d.ctl->nv1;
+    HIPCHK(hipMemcpyAsync(c->ctl_host, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(c->hist_host, d.res_hist, sizeof(double) * (m + 1),
+                          hipMemcpyDeviceToHost, st));
+    if (rec_loo)
+      HIPCHK(hipMemcpyAsync(c->hist_host + (kMaxM + 2), d.loo_hist, sizeof(double) * (m + 1),
+                            hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(c->ev_done, st));
+  }
+
+  // The launches of one cycle, in stream order.
+  void record(int cyc_) {
     Krylov<T>& k = *kp;
     hipStream_t st = c->stream;
     const int s = k.s;
@@ -479,7 +593,6 @@ struct CycleRunner {
     (void)n;
     (void)ctl;
     (void)tm;
-    const int cyc_ = ++cyc;
     hipStream_t side = c->side;
     size_t nev = 0;
     auto event = [&]() -> hipEvent_t {
@@ -506,17 +619,20 @@ struct CycleRunner {
     // `side`, the QR update / convergence test of each finished column on
     // `side2`, one batch behind, so the two chains overlap.
     hipStream_t side2 = c->side2;
+    // streams this cycle forked to (under capture only those may be joined)
+    bool used_side = false, used_side2 = false;
     auto flush_side = [&]() {
       if (pending.empty()) return;
       hipEvent_t e = event();
       HIPCHK(hipEventRecord(e, st));
       HIPCHK(hipStreamWaitEvent(side, e, 0));
+      used_side = true;
       bool any_side = false;
       for (const SideJob& j : pending) {
         if (j.kind == 0) {
           launch_small_finalize(side, d, j.arg, tm);
         } else {
-          launch_small_side(side, d, j.arg, j.mcur, false, tm);
+          launch_small_side(side, d, j.arg, j.mcur, tm);
           any_side = true;
         }
       }
@@ -524,6 +640,7 @@ struct CycleRunner {
         hipEvent_t e2 = event();
         HIPCHK(hipEventRecord(e2, side));
         HIPCHK(hipStreamWaitEvent(side2, e2, 0));
+        used_side2 = true;
         for (const SideJob& j : pending)
           if (j.kind == 1) launch_small_finalize(side2, d, j.arg - 1, tm);
       }
@@ -655,29 +772,24 @@ struct CycleRunner {
     }
     // join the side streams, then end the cycle
     flush_side();
-    {
+    if (used_side) {
       hipEvent_t e = event();
       HIPCHK(hipEventRecord(e, side));
       HIPCHK(hipStreamWaitEvent(st, e, 0));
+    }
+    if (used_side2) {
       hipEvent_t e2 = event();
       HIPCHK(hipEventRecord(e2, side2));
       HIPCHK(hipStreamWaitEvent(st, e2, 0));
     }
     tag(1 << 30, 0);
     launch_small_cycle_end(st, d, tm);
-    uapply = upd_args(k);
-    uapply.in1 = x;
-    uapply.out1 = x;
-    uapply.out2 = k.U;
-    uapply.nvp = &ctl->nv1;
-    launch_update<T>(st, uapply, ctl, false, tm);
-    HIPCHK(hipMemcpyAsync(c->ctl_host, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(c->hist_host, d.res_hist, sizeof(double) * (m + 1),
-                          hipMemcpyDeviceToHost, st));
-    if (rec_loo)
-      HIPCHK(hipMemcpyAsync(c->hist_host + (kMaxM + 2), d.loo_hist, sizeof(double) * (m + 1),
-                            hipMemcpyDeviceToHost, st));
-    HIPCHK(hipEventRecord(c->ev_done, st));
+    UpdateArgs<T> ua = upd_args(k);
+    ua.in1 = x;
+    ua.out1 = x;
+    ua.out2 = k.U;
+    ua.nvp = &ctl->nv1;
+    launch_update<T>(st, ua, ctl, false, tm);
   }
 
   bool finish() {
@@ -1248,6 +1360,14 @@ lsba_status lsba_context_set_timing(lsba_context* c, uint32_t kind_mask) {
   } catch (const HipError& e) {
     return fail(c, LSBA_ERR_HIP, e.msg);
   }
+  return LSBA_OK;
+}
+
+lsba_status lsba_context_set_graphs(lsba_context* c, int enable) {
+  if (!c) return fail(nullptr, LSBA_ERR_ARG, "context is NULL");
+  (void)hipSetDevice(c->device);
+  graphs_clear(c);
+  c->graphs_on = enable != 0;
   return LSBA_OK;
 }
 

@@ -34,7 +34,7 @@ EXPORTS = [
     "lsba_result_true_relres", "lsba_result_refine_steps", "lsba_result_gpu_ms",
     "lsba_result_destroy", "lsba_context_set_timing", "lsba_context_kernel_stats",
     "lsba_solve_footprint", "lsba_server_create", "lsba_server_submit", "lsba_server_poll",
-    "lsba_server_fetch", "lsba_server_stats", "lsba_server_destroy",
+    "lsba_server_fetch", "lsba_server_stats", "lsba_server_destroy", "lsba_context_set_graphs",
 ]
 
 KERNEL_KINDS = {"spmm": 0, "gram": 1, "gram_reduce": 2, "update": 3, "small": 4, "residual": 5}
@@ -108,6 +108,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "lsba_result_gpu_ms": (dbl, [vp]),
         "lsba_result_destroy": (None, [vp]),
         "lsba_context_set_timing": (i32, [vp, ctypes.c_uint32]),
+        "lsba_context_set_graphs": (i32, [vp, ctypes.c_int]),
         "lsba_context_kernel_stats": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                             ctypes.POINTER(dbl)]),
         "lsba_solve_footprint": (ctypes.c_uint64, [i64, i32, vp]),
@@ -167,6 +168,13 @@ class Context:
             for k in kinds:
                 mask |= 1 << KERNEL_KINDS[k]
         st = self.lib.lsba_context_set_timing(self.h, mask)
+        if st != 0:
+            raise LsbaError(st, self.error())
+
+    def set_graphs(self, enable: bool = True):
+        """Replay captured cycles (enable=True) or launch every kernel
+        individually (enable=False, the default)."""
+        st = self.lib.lsba_context_set_graphs(self.h, 1 if enable else 0)
         if st != 0:
             raise LsbaError(st, self.error())
 
