@@ -287,54 +287,65 @@ __global__ __launch_bounds__(NT) void small_core_kernel(Dense d, int k, int m, i
   }
   tri_inv_up(R, s, Ri, dinv);
   double* coef = d.coef64;
+  // C1 = C2 = R^{-1}; H_{k,k-1} = R;  P = R^{-T} (P~ - Y^T Z)
   for (int e = threadIdx.x; e < ss; e += NT) {
     coef[lay.C1() + e] = Ri[e];
     d.H[(int64_t)(r0 + e / s) * ld + (k - 2) * s + (e % s)] = R[e];
     if (!last) {
       coef[lay.C2() + e] = Ri[e];
       d.RiS[(int64_t)k * ss + e] = Ri[e];
-    }
-  }
-  // A = -Y R^{-1}
-  rows_x_small(r0, s, Gp, ldg, Ri, -1.0, coef + lay.A(0), s);
-  if (!last) {
-    // B = -Z R^{-1};  P = R^{-T} (P~ - Y^T Z)
-    rows_x_small(r0, s, Gp + s, ldg, Ri, -1.0, coef + lay.B(0), s);
-    for (int e = threadIdx.x; e < ss; e += NT) {
       const int i = e / s, c = e % s;
       double acc = 0.0;
 #pragma unroll 8
       for (int t = 0; t < s; ++t) acc = fma(Ri[t * s + i], OmP[t * ldg + s + c], acc);
       Pn[e] = acc;
+      d.PS[(int64_t)k * ss + e] = acc;
     }
+  }
+  double* PR = OmP;   // [Omega | ..] is dead once P is formed
+  if (!last) {
     bar();
-    // D = -P R^{-1};  W = R^{-1} P R^{-1}
-    rows_x_small(s, s, Pn, s, Ri, -1.0, coef + lay.D(), s);
-    for (int e = threadIdx.x; e < ss; e += NT) d.PS[(int64_t)k * ss + e] = Pn[e];
+    // PR = P R^{-1} (D = -PR), then W = R^{-1} PR in R (dead after R^{-1})
     for (int e = threadIdx.x; e < ss; e += NT) {
       const int i = e / s, c = e % s;
       double acc = 0.0;
-      for (int t = 0; t < s; ++t) {
-        double pr = 0.0;
-        for (int u = 0; u < s; ++u) pr = fma(Pn[t * s + u], Ri[u * s + c], pr);
-        acc = fma(Ri[i * s + t], pr, acc);
-      }
-      R[e] = acc;   // R is dead after R^{-1}; W lives there
+#pragma unroll 8
+      for (int t = 0; t < s; ++t) acc = fma(Pn[i * s + t], Ri[t * s + c], acc);
+      PR[e] = acc;
+      coef[lay.D() + e] = -acc;
     }
     bar();
-    // folded form: B_i + A_i D = -Z_i R^{-1} + Y_i W,  C1 D = -W
-    for (int e = threadIdx.x; e < r0 * s; e += NT) {
+    for (int e = threadIdx.x; e < ss; e += NT) {
       const int i = e / s, c = e % s;
-      const double* y = Gp + (int64_t)i * ldg;
-      double a0 = 0.0, a1 = 0.0;
+      double acc = 0.0;
 #pragma unroll 8
-      for (int t = 0; t < s; ++t) {
-        a0 = fma(-y[s + t], Ri[t * s + c], a0);
-        a1 = fma(y[t], R[t * s + c], a1);
-      }
-      coef[lay.BF(0) + e] = a0 + a1;
+      for (int t = 0; t < s; ++t) acc = fma(Ri[i * s + t], PR[t * s + c], acc);
+      R[e] = acc;
+      coef[lay.C1D() + e] = -acc;   // C1 D = -W
     }
-    for (int e = threadIdx.x; e < ss; e += NT) coef[lay.C1D() + e] = -R[e];
+  }
+  bar();
+  // one pass over the rows of [Y Z]: A = -Y R^{-1}, B = -Z R^{-1} and the
+  // folded B + A D = -Z R^{-1} + Y W
+  for (int e = threadIdx.x; e < r0 * s; e += NT) {
+    const int i = e / s, c = e % s;
+    const double* y = Gp + (int64_t)i * ldg;
+    double a = 0.0, b = 0.0, f = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < s; ++t) {
+      const double yt = y[t];
+      a = fma(yt, Ri[t * s + c], a);
+      if (!last) {
+        const double zt = y[s + t];
+        b = fma(zt, Ri[t * s + c], b);
+        f = fma(yt, R[t * s + c], f);
+      }
+    }
+    coef[lay.A(0) + e] = -a;
+    if (!last) {
+      coef[lay.B(0) + e] = -b;
+      coef[lay.BF(0) + e] = f - b;
+    }
   }
   bar();
   publish_coef(d);

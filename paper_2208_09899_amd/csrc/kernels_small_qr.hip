@@ -194,20 +194,37 @@ __device__ void cycle_end_regs(const Dense& d, int j, bool want_m, double* lds) 
     const int e = tid + q * NT;
     xr[q] = e < n ? d.g[e] : 0.0;
   }
-  for (int e = tid; e < j * ss; e += NT) {
-    const int b = e / ss, f = e % ss;
-    Dg[e] = d.Rf[(int64_t)(b * s + f / s) * ld + b * s + f % s];
-  }
   {
-    const int nr = (j - 1) * s * s;   // column block j, rows above the diagonal
-    for (int e = tid; e < nr; e += NT)
-      rc0[e] = d.Rf[(int64_t)(e / s) * ld + (j - 1) * s + e % s];
-  }
-  if (want_m)
-    for (int e = tid; e < (j - 1) * 2 * ss; e += NT) {
-      const int i = e / (2 * ss), f = e % (2 * ss);
-      Qs[e] = d.Qt[(int64_t)i * 4 * ss + 2 * ss + f];
+    // one batched gather: diagonal blocks, column block j above its
+    // diagonal, rows s..2s of each Q_i^T
+    const int nD = j * ss, nR = (j - 1) * ss, nQ = want_m ? (j - 1) * 2 * ss : 0;
+    const int tot = nD + nR + nQ;
+    for (int base = tid; base < tot; base += NT * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int e = base + u * NT;
+        e = e < tot ? e : tot - 1;
+        const double* p;
+        if (e < nD) {
+          const int b = e / ss, f = e % ss;
+          p = d.Rf + (int64_t)(b * s + f / s) * ld + b * s + f % s;
+        } else if (e < nD + nR) {
+          const int f = e - nD;
+          p = d.Rf + (int64_t)(f / s) * ld + (j - 1) * s + f % s;
+        } else {
+          const int f = e - nD - nR, i = f / (2 * ss);
+          p = d.Qt + (int64_t)i * 4 * ss + 2 * ss + f % (2 * ss);
+        }
+        v[u] = *p;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * NT;
+        if (e < tot) lds[e < nD ? e : (e < nD + nR ? 2 * nD + (e - nD) : (Qs - lds) + (e - nD - nR))] = v[u];
+      }
     }
+  }
   bar();
   // inverses of the diagonal blocks: thread (b, c) solves R_bb x = e_c
   if (tid < j * s) {
@@ -238,33 +255,55 @@ __device__ void cycle_end_regs(const Dense& d, int j, bool want_m, double* lds) 
     coefA[(int64_t)(j - 1) * ss + e] = x;
   }
   bar();
+  // Thread tid owns entries e = tid + q NT of Xi (row e / s, column tid % s
+  // for every q: NT is a multiple of s for the power-of-two block sizes; other
+  // s take the column per entry).  Column block b - 1 is fetched into
+  // registers one step ahead (barriers do not wait for global loads).
   double* cur = rc0;
   double* nxt = rc1;
-  for (int b = j; b >= 2; --b) {
-    // rows above block b take column block b; fetch column block b - 1
-    const int top = (b - 1) * s;     // rows updated: a < top
-    const int nn = (b - 2) * s * s;  // column block b - 1, rows above its diagonal
-    double pf[kCeRegs];
+  double pfa[kCeRegs], pfb[kCeRegs];
+  auto fetch = [&](int cb, double (&pf)[kCeRegs]) {   // column block cb, rows above its diagonal
+    const int nn = cb >= 2 ? (cb - 1) * ss : 0;
 #pragma unroll
     for (int q = 0; q < kCeRegs; ++q) {
       const int e = tid + q * NT;
-      pf[q] = e < nn ? d.Rf[(int64_t)(e / s) * ld + (b - 2) * s + e % s] : 0.0;
+      pf[q] = e < nn ? d.Rf[(int64_t)(e / s) * ld + (cb - 1) * s + e % s] : 0.0;
     }
+  };
+  auto step = [&](int b, double (&pst)[kCeRegs], double (&pld)[kCeRegs]) {
+    // rows above block b take column block b (cur); block b - 1 (in pst)
+    // goes to LDS; block b - 2 is fetched into pld
+    fetch(b - 2, pld);
+    const int top = (b - 1) * s;
+    // column tid % s of the solved block, in registers for s <= 8
+    constexpr int kXc = 8;
+    double xc[kXc];
+    const int cc = tid % s;
+#pragma unroll
+    for (int t = 0; t < kXc; ++t) xc[t] = t < s ? xb[t * s + cc] : 0.0;
 #pragma unroll
     for (int q = 0; q < kCeRegs; ++q) {
       const int e = tid + q * NT;
       const int a = e / s, c = e % s;
       if (a < top) {
         double x = xr[q];
-        for (int t = 0; t < s; ++t) x = fma(-cur[a * s + t], xb[t * s + c], x);
+        const double* ra = cur + a * s;
+        if (c == cc && s <= kXc) {
+#pragma unroll
+          for (int t = 0; t < kXc; ++t)
+            if (t < s) x = fma(-ra[t], xc[t], x);
+        } else {
+          for (int t = 0; t < s; ++t) x = fma(-ra[t], xb[t * s + c], x);
+        }
         xr[q] = x;
         if (a >= top - s) xn[(a - (top - s)) * s + c] = x;
       }
     }
+    const int nn = (b - 2) * ss;
 #pragma unroll
     for (int q = 0; q < kCeRegs; ++q) {
       const int e = tid + q * NT;
-      if (e < nn) nxt[e] = pf[q];
+      if (e < nn) nxt[e] = pst[q];
     }
     bar();
     // block b - 1 = R_{b-1,b-1}^{-1} (its updated right-hand side)
@@ -280,6 +319,11 @@ __device__ void cycle_end_regs(const Dense& d, int j, bool want_m, double* lds) 
     double* t = cur;
     cur = nxt;
     nxt = t;
+  };
+  fetch(j - 1, pfa);
+  for (int b = j; b >= 2; b -= 2) {
+    step(b, pfa, pfb);
+    if (b - 1 >= 2) step(b - 1, pfb, pfa);
   }
   if (!want_m) return;
   // S = D^{-T} (H_{j+1,j}^T H_{j+1,j})

@@ -548,16 +548,17 @@ __device__ __forceinline__ void finalize_column(const Dense& d, int j, double* l
       const int f = e - 2 * ss;
       return ring + (int64_t)(f / ss) * slot_sz + q4 + (f % ss);
     };
-    for (int base = threadIdx.x; base < tot; base += NT * 8) {
-      double va[8], vb[8];
+    constexpr int U = 16;
+    for (int base = threadIdx.x; base < tot; base += NT * U) {
+      double va[U], vb[U];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int e = base + u * NT;
         va[u] = *srcA(e < totA ? e : totA - 1);
         vb[u] = *srcB(e < totB ? e : totB - 1);
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int e = base + u * NT;
         if (e < totA) *dstA(e) = va[u];
         if (e < totB) *dstB(e) = vb[u];

@@ -646,14 +646,17 @@ struct CycleRunner {
       }
       pending.clear();
     };
-    auto finalize_after = [&](int col) {
+    // In the last kSideBatch loop steps of the cycle every step is released
+    // at once, so that after the last basis kernel only one job of the
+    // chain is left to run before the cycle end.
+    auto finalize_after = [&](int col, int kk) {
       pending.push_back({0, col, 0});
-      if ((int)pending.size() >= kSideBatch) flush_side();
+      if ((int)pending.size() >= kSideBatch || kk > m - kSideBatch) flush_side();
     };
     // Alg. 7: H column, J recurrence and the test of column kk - 1, off the basis path
     auto side_after = [&](int kk, int mcur) {
       pending.push_back({1, kk, mcur});
-      if ((int)pending.size() >= kSideBatch) flush_side();
+      if ((int)pending.size() >= kSideBatch || kk > m - kSideBatch) flush_side();
     };
     auto gslot = [&](int kk) { return d.G + (int64_t)kk * d.gstride; };
     auto tag = [&](int step, int phase) {
@@ -703,7 +706,7 @@ struct CycleRunner {
         tag(kk, 1);
         if (kk >= 2) {
           if (bcgs) side_after(kk, m);
-          else finalize_after(kk - 1);
+          else finalize_after(kk - 1, kk);
         }
         UpdateArgs<T> u = upd_args(k);
         if (kk == 1) {
@@ -762,7 +765,7 @@ struct CycleRunner {
         }
         launch_gram<T>(st, gram_args<T>(k, kk, {}, {slot(k, kk)}), k.partial, d.G, ctl, tm);
         launch_small_svl_z(st, d, kk, tm);
-        finalize_after(kk);
+        finalize_after(kk, kk);
         if (rec_loo) {
           launch_gram<T>(st, gram_args<T>(k, kk + 1, {}, {slot(k, kk)}), k.partial, d.G2, ctl,
                          tm);
