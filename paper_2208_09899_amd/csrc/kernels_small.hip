@@ -26,6 +26,8 @@
 // factors are prefetched into LDS (all of them when they fit, else a
 // double-buffered ring), and small products split their reduction across
 // threads when they have few outputs.
+#include <algorithm>
+
 #include "small_common.h"
 
 namespace lsba {
@@ -33,6 +35,16 @@ namespace lsba {
 namespace {
 
 // ------------------------------------------------------------------ kernels
+
+// T = T^T = I at the start of a cycle (Algs. 5 and 6), spread over the chip.
+__global__ __launch_bounds__(NT) void t_identity_kernel(Dense d) {
+  const int64_t ld = d.ldh, tot = ld * ld;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * NT) {
+    const double v = ((e / ld) == (e % ld)) ? 1.0 : 0.0;
+    d.T[e] = v;
+    d.Tt[e] = v;
+  }
+}
 
 __global__ __launch_bounds__(NT) void small_start_kernel(Dense d, int force) {
   __shared__ double lds[4 * kMaxS * kMaxS];
@@ -42,13 +54,6 @@ __global__ __launch_bounds__(NT) void small_start_kernel(Dense d, int force) {
   double* R = lds;
   double* Ri = lds + ss;
   double* G = lds + 2 * ss;
-  const bool needT = d.skel != LSBA_BCGSI_LS;
-  if (needT)
-    for (int64_t e = threadIdx.x; e < (int64_t)ld * ld; e += NT) {
-      const double v = ((e / ld) == (e % ld)) ? 1.0 : 0.0;
-      d.T[e] = v;
-      d.Tt[e] = v;
-    }
   for (int e = threadIdx.x; e < ss; e += NT) G[e] = d.G[e];
   bar();
   bool ok = chol_flag(d, G, s, R);
@@ -372,6 +377,212 @@ __host__ __device__ inline bool cwy_fits(int s, int k) {
 // R^{-1}) (ICWY) with T = T_{1:k,1:k}, and the coefficients of V_k = U R^{-1}
 // and U = W R^{-1} - V_{1:k} H_{1:k,k}.  T is read from global memory once,
 // staged in LDS a few rows (CWY) or column blocks (ICWY) at a time.
+// LDS doubles small_cwy_rows needs at loop step k.
+__host__ __device__ inline int cwy_rows_lds(int s, int k) {
+  const int r0 = (k - 1) * s;
+  return 6 * r0 * s + 6 * s * s + NT;
+}
+
+// Alg. 6 with the explicit T (BMGS-CWY), loop step 2 <= k <= m, split over
+// the k block rows: workgroup rb < k - 1 forms block row rb of the new T
+// column T_{1:k-1,k} = -T (Y R^{-1}) and of H_{1:k-1,k} = T^T (Z R^{-1}) (each
+// needs only its own rows of T, T^T and [Y Z]; every workgroup repeats the
+// s x s Cholesky), workgroup k - 1 writes R and the R^{-1} coefficients.  The
+// last block row H_{k,k} = P R^{-1} + T_{1:k-1,k}^T (Z R^{-1}) sums one s x s
+// term per block row: each workgroup stores its term, and the workgroup that
+// arrives last (a counter per loop step) adds them in block-row order.
+__global__ __launch_bounds__(NT) void small_cwy_rows_kernel(Dense d, int k, int force) {
+  __shared__ double lds[LDS_DBL];
+  __shared__ int is_last;
+  Ctl* ctl = d.ctl;
+  if (ctl->stop) return;
+  const int s = d.s, ld = d.ldh, ss = s * s;
+  CoefLayout lay{s, d.mmax + 1};
+  const int r0 = (k - 1) * s, ldg = 2 * s;
+  const int rb = blockIdx.x, a0 = rb * s;
+  const bool rowblk = rb < k - 1;
+  const double* Gk = d.G + (int64_t)k * d.gstride;
+  const Scr sc = make_scr(d);
+  double* part = sc.bg(2);          // (k - 1) x ss terms of the last block row
+  const int tid = threadIdx.x;
+  double* Om = lds;                 // ss  Omega
+  double* Pt = Om + ss;             // ss  P~
+  double* R = Pt + ss;              // ss
+  double* Ri = R + ss;              // ss
+  double* Pn = Ri + ss;             // ss  P = R^{-T} P~
+  double* dv = Pn + ss;             // ss  (s used: 1 / R_ii)
+  double* red = dv + ss;            // NT  split-sum partials
+  double* Gs = red + NT;            // r0 x 2s  [Y Z]
+  const int wT = r0 - a0, wH = a0 + s;
+  double* Tr = Gs + 2 * r0 * s;     // s x wT   T(a0 + i, a0 + u)
+  double* Ttr = Tr + s * r0;        // s x wH   T^T(a0 + i, t)
+  double* YR = Ttr + s * r0;        // r0 x s   (rows a0 .. r0 used)
+  double* ZR = YR + r0 * s;         // r0 x s   (rows 0 .. a0 + s used)
+  {
+    const int nA = 2 * ss, nG = 2 * r0 * s, nT = rowblk ? s * wT : 0, nH = rowblk ? s * wH : 0;
+    const int tot = nA + nG + nT + nH;
+    for (int base = tid; base < tot; base += NT * 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        int e = base + u * NT;
+        e = e < tot ? e : tot - 1;
+        const double* p;
+        if (e < nA) {
+          const int f = e % ss;
+          p = Gk + (int64_t)(r0 + f / s) * ldg + (e < ss ? 0 : s) + f % s;
+        } else if (e < nA + nG) {
+          p = Gk + (e - nA);
+        } else if (e < nA + nG + nT) {
+          const int f = e - nA - nG;
+          p = d.T + (int64_t)(a0 + f / wT) * ld + a0 + f % wT;
+        } else {
+          const int f = e - nA - nG - nT;
+          p = d.Tt + (int64_t)(a0 + f / wH) * ld + f % wH;
+        }
+        v[u] = *p;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = base + u * NT;
+        if (e < tot) {
+          double* q;
+          if (e < nA) q = Om + e;                                  // Om, Pt adjacent
+          else if (e < nA + nG) q = Gs + (e - nA);
+          else if (e < nA + nG + nT) q = Tr + (e - nA - nG);
+          else q = Ttr + (e - nA - nG - nT);
+          *q = v[u];
+        }
+      }
+    }
+  }
+  bar();
+  bool ok = chol_flag(d, Om, s, R, dv);
+  if (force) ok = false;
+  if (!ok) {
+    if (rb == 0 && tid == 0) raise_flag(ctl, k, k - 2);
+    return;
+  }
+  tri_inv_up(R, s, Ri, dv);
+  double* coef = d.coef64;
+  for (int e = tid; e < ss; e += NT) {
+    const int i = e / s, c = e % s;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < s; ++t) acc = fma(Ri[t * s + i], Pt[t * s + c], acc);
+    Pn[e] = acc;
+    if (!rowblk) {
+      d.H[(int64_t)(r0 + i) * ld + (k - 2) * s + c] = R[e];
+      coef[lay.C1() + e] = Ri[e];
+      coef[lay.C2() + e] = Ri[e];
+    }
+  }
+  // Y R^{-1} on rows a0 .. r0, Z R^{-1} on rows 0 .. a0 + s
+  if (rowblk) {
+    const int ny = wT * s, nz = wH * s;
+    for (int e = tid; e < ny + nz; e += NT) {
+      const bool isy = e < ny;
+      const int f = isy ? e : e - ny;
+      const int row = isy ? a0 + f / s : f / s, c = f % s;
+      const double* g = Gs + row * ldg + (isy ? 0 : s);
+      double acc = 0.0;
+#pragma unroll 8
+      for (int t = 0; t < s; ++t) acc = fma(g[t], Ri[t * s + c], acc);
+      (isy ? YR : ZR)[row * s + c] = acc;
+    }
+  }
+  bar();
+  if (rowblk) {
+    // Tc = -T(rows, a0:r0) YR(a0:r0),  Hc = T^T(rows, 0:a0+s) ZR(0:a0+s), the
+    // sums split over kp parts when s^2 < NT and added in part order
+    const int kp = ss >= NT ? 1 : NT / ss;
+    const int pt = ss >= NT ? 0 : tid / ss;
+    constexpr int kQ = kMaxS * kMaxS / NT;
+    double at[kQ], ah[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) at[q] = ah[q] = 0.0;
+    if (pt < kp) {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const int e = ss >= NT ? tid + q * NT : tid % ss;
+        if (e < ss && (q == 0 || ss >= NT)) {
+          const int i = e / s, c = e % s;
+          double x = 0.0, y = 0.0;
+          for (int u = pt; u < wT; u += kp) x = fma(Tr[i * wT + u], YR[(a0 + u) * s + c], x);
+          for (int t = pt; t < wH; t += kp) y = fma(Ttr[i * wH + t], ZR[t * s + c], y);
+          at[q] = x;
+          ah[q] = y;
+        }
+      }
+    }
+    double* Tc = Om;   // Omega, P~ are dead: Tc, Hc (ss each) live there
+    double* Hc = Pt;
+    if (kp > 1) {
+      for (int pass = 0; pass < 2; ++pass) {
+        bar();
+        if (pt < kp) red[pt * ss + tid % ss] = pass == 0 ? at[0] : ah[0];
+        bar();
+        for (int e = tid; e < ss; e += NT) {
+          double sum = 0.0;
+          for (int p = 0; p < kp; ++p) sum += red[p * ss + e];
+          (pass == 0 ? Tc : Hc)[e] = pass == 0 ? -sum : sum;
+        }
+      }
+    } else {
+      bar();
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const int e = tid + q * NT;
+        if (e < ss) {
+          Tc[e] = -at[q];
+          Hc[e] = ah[q];
+        }
+      }
+    }
+    bar();
+    for (int e = tid; e < ss; e += NT) {
+      const int i = e / s, c = e % s, a = a0 + i;
+      d.H[(int64_t)a * ld + (k - 1) * s + c] = Hc[e];
+      coef[lay.B(0) + a * s + c] = -Hc[e];
+      coef[lay.BF(0) + a * s + c] = -Hc[e];   // folded form: no A blocks (V_k = U R^{-1})
+      d.T[(int64_t)a * ld + r0 + c] = Tc[e];
+      d.Tt[(int64_t)(r0 + c) * ld + a] = Tc[e];
+      // this block row's term of T_{1:k-1,k}^T (Z R^{-1}): Tc^T ZR(rows)
+      double acc = 0.0;
+      for (int t = 0; t < s; ++t) acc = fma(Tc[t * s + i], ZR[(a0 + t) * s + c], acc);
+      part[(int64_t)rb * ss + e] = acc;
+    }
+  }
+  // arrival: the last workgroup of this loop step finishes the column
+  __threadfence();
+  bar();
+  if (tid == 0) is_last = (atomicAdd(&ctl->arrive[k], 1) == k - 1) ? 1 : 0;
+  bar();
+  if (!is_last) return;
+  __threadfence();
+  if (tid == 0) ctl->arrive[k] = 0;
+  double* Hl = red;   // ss (red is free)
+  for (int e = tid; e < ss; e += NT) {
+    const int i = e / s, c = e % s;
+    double acc = 0.0;
+    for (int t = 0; t < s; ++t) acc = fma(Pn[i * s + t], Ri[t * s + c], acc);   // P R^{-1}
+    for (int b = 0; b < k - 1; ++b) acc += part[(int64_t)b * ss + e];
+    Hl[e] = acc;
+    d.H[(int64_t)(r0 + i) * ld + (k - 1) * s + c] = acc;
+    coef[lay.D() + e] = -acc;
+  }
+  bar();
+  // C1 D = -R^{-1} H_{k,k}
+  for (int e = tid; e < ss; e += NT) {
+    const int i = e / s, c = e % s;
+    double acc = 0.0;
+    for (int t = 0; t < s; ++t) acc = fma(Ri[i * s + t], Hl[t * s + c], acc);
+    coef[lay.C1D() + e] = -acc;
+  }
+  bar();
+  publish_coef(d);
+}
+
 template <bool ICWY>
 __global__ __launch_bounds__(NT) void small_cwy_kernel(Dense d, int k, int force) {
   __shared__ double lds[LDS_DBL];
@@ -653,10 +864,19 @@ __global__ __launch_bounds__(NT) void small_svl_z_kernel(Dense d, int k) {
   } while (0)
 
 void launch_small_start(hipStream_t st, const Dense& d, int force_flag, KTimer* tm) {
+  if (d.skel != LSBA_BCGSI_LS) {
+    const int64_t tot = (int64_t)d.ldh * d.ldh;
+    const int blocks = (int)std::min<int64_t>((tot + NT - 1) / NT, 1024);
+    SMALL_LAUNCH(t_identity_kernel<<<blocks, NT, 0, st>>>(d));
+  }
   SMALL_LAUNCH(small_start_kernel<<<1, NT, 0, st>>>(d, force_flag));
 }
 void launch_small_delayed(hipStream_t st, const Dense& d, int k, int m, int force_flag,
                           KTimer* tm) {
+  if (d.skel == LSBA_BMGS_CWY && k >= 2 && k <= m && cwy_rows_lds(d.s, k) <= LDS_DBL) {
+    SMALL_LAUNCH(small_cwy_rows_kernel<<<k, NT, 0, st>>>(d, k, force_flag));
+    return;
+  }
   if (d.skel != LSBA_BCGSI_LS && k >= 2 && k <= m && cwy_fits(d.s, k)) {
     if (d.skel == LSBA_BMGS_ICWY)
       SMALL_LAUNCH(small_cwy_kernel<true><<<1, NT, 0, st>>>(d, k, force_flag));

@@ -373,6 +373,8 @@ __global__ __launch_bounds__(NT) void small_cycle_end_kernel(Dense d) {
     ctl->cycles += 1;
     ctl->cyc_status = status;
   }
+  // arrival counters of split small steps left behind by an early stop
+  for (int i = threadIdx.x; i < kMaxM + 2; i += NT) ctl->arrive[i] = 0;
   if (j == 0) {
     // nothing to apply: nv1 = -1 tells the basis application to leave X and U alone
     if (threadIdx.x == 0) {

@@ -48,6 +48,7 @@ struct Ctl {
   double nB;            // ||B||_F of the right-hand side of this solve
   double tol;
   double est;           // last relative residual estimate
+  int arrive[kMaxM + 2];   // per loop step: workgroups of a split small step done
 };
 
 // Small dense state of one solve (FP64, device, row-major).
