@@ -583,6 +583,203 @@ __global__ __launch_bounds__(NT) void small_cwy_rows_kernel(Dense d, int k, int 
   publish_coef(d);
 }
 
+// Register-resident BMGS-ICWY step: used when the k s x s block column fits
+// kIcRegs doubles per thread and its operands fit in LDS.
+constexpr int kIcRegs = 8;
+__host__ __device__ inline bool icwy_fast(int s, int k) {
+  const int r0 = (k - 1) * s, ss = s * s;
+  return k * ss <= kIcRegs * NT && 9 * ss + 5 * r0 * s <= LDS_DBL;
+}
+
+// Alg. 6 with the inverse compact WY form (BMGS-ICWY), loop step 2 <= k <= m:
+// H_{1:k,k} = X solves T^T X = [Z; P] R^{-1} with T unit block upper
+// triangular, its new column block being Y R^{-1}.  Block forward
+// substitution, right-looking: once X_b is final, the right-hand sides of the
+// later block rows take T(b, c)^T X_b at once, each thread updating the
+// entries it owns (in registers).  T(b, c) for c <= k - 2 is read as rows of
+// T^T, fetched two steps ahead; T(b, k - 1) is Y R^{-1} (LDS).
+__global__ __launch_bounds__(NT) void small_icwy_kernel(Dense d, int k, int force) {
+  __shared__ double lds[LDS_DBL];
+  Ctl* ctl = d.ctl;
+  if (ctl->stop) return;
+  const int s = d.s, ld = d.ldh, ss = s * s;
+  CoefLayout lay{s, d.mmax + 1};
+  const int r0 = (k - 1) * s, ks = k * s, ldg = 2 * s;
+  const double* Gk = d.G + (int64_t)k * d.gstride;
+  const int tid = threadIdx.x;
+  double* Om = lds;              // ss  Omega
+  double* Pt = Om + ss;          // ss  P~
+  double* R = Pt + ss;           // ss
+  double* Ri = R + ss;           // ss
+  double* Pn = Ri + ss;          // ss
+  double* dv = Pn + ss;          // ss
+  double* xb = dv + ss;          // ss  X_b
+  double* xn = xb + ss;          // ss  X_{b+1}
+  double* Hl = xn + ss;          // ss  X_{k-1}
+  double* Gs = Hl + ss;          // r0 x 2s  [Y Z]
+  double* YR = Gs + 2 * r0 * s;  // r0 x s
+  double* c0b = YR + r0 * s;     // r0 x s   rows of T^T for one step
+  double* c1b = c0b + r0 * s;    // r0 x s
+  // T^T rows (b+1)s .. r0, columns bs .. bs+s: the step-b terms T(b, c), c <= k-2
+  auto nstep = [&](int b) { return b <= k - 3 ? (r0 - (b + 1) * s) * s : 0; };
+  {
+    const int nA = 2 * ss, nG = 2 * r0 * s, n0 = nstep(0);
+    const int tot = nA + nG + n0;
+    for (int base = tid; base < tot; base += NT * 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        int e = base + u * NT;
+        e = e < tot ? e : tot - 1;
+        const double* p;
+        if (e < nA) {
+          const int f = e % ss;
+          p = Gk + (int64_t)(r0 + f / s) * ldg + (e < ss ? 0 : s) + f % s;
+        } else if (e < nA + nG) {
+          p = Gk + (e - nA);
+        } else {
+          const int f = e - nA - nG;
+          p = d.Tt + (int64_t)(s + f / s) * ld + f % s;
+        }
+        v[u] = *p;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = base + u * NT;
+        if (e < tot) {
+          double* q;
+          if (e < nA) q = Om + e;
+          else if (e < nA + nG) q = Gs + (e - nA);
+          else q = c0b + (e - nA - nG);
+          *q = v[u];
+        }
+      }
+    }
+  }
+  bar();
+  bool ok = chol_flag(d, Om, s, R, dv);
+  if (force) ok = false;
+  if (!ok) {
+    if (tid == 0) raise_flag(ctl, k, k - 2);
+    return;
+  }
+  tri_inv_up(R, s, Ri, dv);
+  double* coef = d.coef64;
+  for (int e = tid; e < ss; e += NT) {
+    const int i = e / s, c = e % s;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < s; ++t) acc = fma(Ri[t * s + i], Pt[t * s + c], acc);
+    Pn[e] = acc;
+    d.H[(int64_t)(r0 + i) * ld + (k - 2) * s + c] = R[e];
+    coef[lay.C1() + e] = Ri[e];
+    coef[lay.C2() + e] = Ri[e];
+  }
+  for (int e = tid; e < r0 * s; e += NT) {
+    const int a = e / s, c = e % s;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < s; ++t) acc = fma(Gs[a * ldg + t], Ri[t * s + c], acc);
+    YR[e] = acc;
+  }
+  bar();
+  // right-hand sides [Z; P] R^{-1}, entries e = tid + q NT (row e / s)
+  double xr[kIcRegs];
+#pragma unroll
+  for (int q = 0; q < kIcRegs; ++q) {
+    const int e = tid + q * NT;
+    const int a = e / s, c = e % s;
+    double acc = 0.0;
+    if (e < ks * s) {
+      const double* g = a < r0 ? Gs + a * ldg + s : Pn + (a - r0) * s;
+      for (int t = 0; t < s; ++t) acc = fma(g[t], Ri[t * s + c], acc);
+    }
+    xr[q] = acc;
+    if (a < s && e < ks * s) xb[e] = acc;   // X_0
+  }
+  double* cur = c0b;
+  double* nxt = c1b;
+  double pfa[kIcRegs], pfb[kIcRegs];
+  auto fetch = [&](int b, double (&pf)[kIcRegs]) {
+    const int nn = nstep(b);
+#pragma unroll
+    for (int q = 0; q < kIcRegs; ++q) {
+      const int e = tid + q * NT;
+      pf[q] = e < nn ? d.Tt[(int64_t)((b + 1) * s + e / s) * ld + b * s + e % s] : 0.0;
+    }
+  };
+  auto step = [&](int b, double (&pst)[kIcRegs], double (&pld)[kIcRegs]) {
+    bar();   // X_b (xb) and the step-b rows of T^T (cur) are in LDS
+    fetch(b + 2, pld);
+    const int lo = (b + 1) * s;
+#pragma unroll
+    for (int q = 0; q < kIcRegs; ++q) {
+      const int e = tid + q * NT;
+      const int a = e / s, c = e % s;
+      if (a >= lo && e < ks * s) {
+        double x = xr[q];
+        if (a < r0) {
+          const double* tr = cur + (a - lo) * s;
+          for (int t = 0; t < s; ++t) x = fma(-tr[t], xb[t * s + c], x);
+        } else {
+          for (int t = 0; t < s; ++t) x = fma(-YR[(b * s + t) * s + (a - r0)], xb[t * s + c], x);
+        }
+        xr[q] = x;
+        if (a < lo + s) xn[(a - lo) * s + c] = x;
+      }
+    }
+    const int nn = nstep(b + 1);
+#pragma unroll
+    for (int q = 0; q < kIcRegs; ++q) {
+      const int e = tid + q * NT;
+      if (e < nn) nxt[e] = pst[q];
+    }
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+    t = xb;
+    xb = xn;
+    xn = t;
+  };
+  fetch(1, pfa);
+  for (int b = 0; b <= k - 2; b += 2) {
+    step(b, pfa, pfb);
+    if (b + 1 <= k - 2) step(b + 1, pfb, pfa);
+  }
+  // H_{1:k,k} = X, the coefficients, the new T column Y R^{-1}
+#pragma unroll
+  for (int q = 0; q < kIcRegs; ++q) {
+    const int e = tid + q * NT;
+    if (e < ks * s) {
+      const int a = e / s, c = e % s;
+      const double x = xr[q];
+      d.H[(int64_t)a * ld + (k - 1) * s + c] = x;
+      if (a < r0) {
+        coef[lay.B(0) + e] = -x;
+        coef[lay.BF(0) + e] = -x;   // folded form: no A blocks (V_k = U R^{-1})
+      } else {
+        coef[lay.D() + (e - r0 * s)] = -x;
+        Hl[e - r0 * s] = x;
+      }
+    }
+  }
+  for (int e = tid; e < r0 * s; e += NT) {
+    const int a = e / s, c = e % s;
+    d.T[(int64_t)a * ld + r0 + c] = YR[e];
+    d.Tt[(int64_t)(r0 + c) * ld + a] = YR[e];
+  }
+  bar();
+  // C1 D = -R^{-1} H_{k,k}
+  for (int e = tid; e < ss; e += NT) {
+    const int i = e / s, c = e % s;
+    double acc = 0.0;
+    for (int t = 0; t < s; ++t) acc = fma(Ri[i * s + t], Hl[t * s + c], acc);
+    coef[lay.C1D() + e] = -acc;
+  }
+  bar();
+  publish_coef(d);
+}
+
 template <bool ICWY>
 __global__ __launch_bounds__(NT) void small_cwy_kernel(Dense d, int k, int force) {
   __shared__ double lds[LDS_DBL];
@@ -875,6 +1072,10 @@ void launch_small_delayed(hipStream_t st, const Dense& d, int k, int m, int forc
                           KTimer* tm) {
   if (d.skel == LSBA_BMGS_CWY && k >= 2 && k <= m && cwy_rows_lds(d.s, k) <= LDS_DBL) {
     SMALL_LAUNCH(small_cwy_rows_kernel<<<k, NT, 0, st>>>(d, k, force_flag));
+    return;
+  }
+  if (d.skel == LSBA_BMGS_ICWY && k >= 2 && k <= m && icwy_fast(d.s, k)) {
+    SMALL_LAUNCH(small_icwy_kernel<<<1, NT, 0, st>>>(d, k, force_flag));
     return;
   }
   if (d.skel != LSBA_BCGSI_LS && k >= 2 && k <= m && cwy_fits(d.s, k)) {
