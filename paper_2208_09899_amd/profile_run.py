@@ -26,9 +26,10 @@ if __package__ in (None, ""):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 
-KERNEL_CLASSES = {"update": ("update_kernel", "kernels_update.hip"),
-                  "gram": ("gram_stage1", "kernels_gram.hip"),
-                  "spmm": ("spmm_kernel", "kernels_sparse.hip")}
+# kernel class: (kernel-name substrings, source file)
+KERNEL_CLASSES = {"update": (("update_kernel", "update_mfma8"), "kernels_update.hip"),
+                  "gram": (("gram_stage1", "gram_mfma"), "kernels_gram.hip"),
+                  "spmm": (("spmm_kernel",), "kernels_sparse.hip")}
 
 
 def _counter_means(path, counter):
@@ -63,8 +64,8 @@ def summarize(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, alg_json, wo
     rec = {"workload": workload, "fetch_scale": fscale, "write_scale": wscale,
            "copy_bytes": copy_bytes, "kernels": {}}
     for cls, (sub, src) in KERNEL_CLASSES.items():
-        fk = [v for k, v in fe.items() if sub in k]
-        wk = [v for k, v in wr.items() if sub in k]
+        fk = [v for k, v in fe.items() if any(x in k for x in sub)]
+        wk = [v for k, v in wr.items() if any(x in k for x in sub)]
         if not fk or not wk or not alg.get(cls, {}).get("launches"):
             continue
         n = sum(c for _, c in fk)
