@@ -307,10 +307,8 @@ static void launch_stage2(hipStream_t st, const double* partial, int nchunk, int
   // entries per workgroup: 8 .. 64, aiming at >= 256 workgroups
   int ewl = 3;
   while (ewl < 6 && ((entries + (1 << ewl) - 1) >> ewl) > 256) ++ewl;
-  if (tm) tm->begin(st, KK_GRAM_REDUCE);
-  gram_stage2<<<dim3((entries + (1 << ewl) - 1) >> ewl), dim3(256), 0, st>>>(
-      partial, nchunk, entries, ewl, out, ctl);
-  if (tm) tm->end(st, KK_GRAM_REDUCE, 0.0);
+  launch_k(tm, KK_GRAM_REDUCE, 0.0, gram_stage2, dim3((entries + (1 << ewl) - 1) >> ewl),
+           dim3(256), 0, st, partial, nchunk, entries, ewl, out, ctl);
 }
 
 // Distinct input blocks of a Gram launch (a right block that is also a left
@@ -336,10 +334,9 @@ void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* 
     if (use_mfma(a.s)) {
       const MPlan q = mplan(a.n, PA, QB);
       const int nchunk_pad = ((q.nchunk + kXcds - 1) / kXcds) * kXcds;
-      if (tm) tm->begin(st, KK_GRAM);
-      gram_mfma_f64<<<dim3(nchunk_pad * q.ngroup), dim3(256), 0, st>>>(
-          a, q.nchunk, q.ngroup, q.rows, partial, ctl);
-      if (tm) tm->end(st, KK_GRAM, (double)distinct_blocks(a) * a.n * a.s * sizeof(T));
+      launch_k(tm, KK_GRAM, (double)distinct_blocks(a) * a.n * a.s * sizeof(T), gram_mfma_f64,
+               dim3(nchunk_pad * q.ngroup), dim3(256), 0, st, a, q.nchunk, q.ngroup, q.rows,
+               partial, ctl);
       launch_stage2(st, partial, q.nchunk, PA * QB, out, ctl, tm);
       return;
     }
@@ -347,25 +344,24 @@ void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* 
   const Plan p = plan(a.n, a.s, PA, QB);
   const int nchunk_pad = ((p.nchunk + kXcds - 1) / kXcds) * kXcds;
   const int blocks = nchunk_pad * p.ngroup;
-  if (tm) tm->begin(st, KK_GRAM);
+  const double bytes = (double)distinct_blocks(a) * a.n * a.s * sizeof(T);
   switch (p.tl) {
     case 8:
-      gram_stage1<T, 8><<<dim3(blocks), dim3(256), 0, st>>>(a, p.nchunk, p.ngroup, p.rows,
-                                                            partial, ctl);
+      launch_k(tm, KK_GRAM, bytes, gram_stage1<T, 8>, dim3(blocks), dim3(256), 0, st, a, p.nchunk,
+               p.ngroup, p.rows, partial, ctl);
       break;
     case 4:
-      gram_stage1<T, 4><<<dim3(blocks), dim3(256), 0, st>>>(a, p.nchunk, p.ngroup, p.rows,
-                                                            partial, ctl);
+      launch_k(tm, KK_GRAM, bytes, gram_stage1<T, 4>, dim3(blocks), dim3(256), 0, st, a, p.nchunk,
+               p.ngroup, p.rows, partial, ctl);
       break;
     case 2:
-      gram_stage1<T, 2><<<dim3(blocks), dim3(256), 0, st>>>(a, p.nchunk, p.ngroup, p.rows,
-                                                            partial, ctl);
+      launch_k(tm, KK_GRAM, bytes, gram_stage1<T, 2>, dim3(blocks), dim3(256), 0, st, a, p.nchunk,
+               p.ngroup, p.rows, partial, ctl);
       break;
     default:
-      gram_stage1<T, 1><<<dim3(blocks), dim3(256), 0, st>>>(a, p.nchunk, p.ngroup, p.rows,
-                                                            partial, ctl);
+      launch_k(tm, KK_GRAM, bytes, gram_stage1<T, 1>, dim3(blocks), dim3(256), 0, st, a, p.nchunk,
+               p.ngroup, p.rows, partial, ctl);
   }
-  if (tm) tm->end(st, KK_GRAM, (double)distinct_blocks(a) * a.n * a.s * sizeof(T));
   launch_stage2(st, partial, p.nchunk, PA * QB, out, ctl, tm);
 }
 template void launch_gram<double>(hipStream_t, const GramArgs<double>&, double*, double*,

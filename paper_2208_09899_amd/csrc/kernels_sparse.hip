@@ -116,11 +116,10 @@ void launch_spmm(hipStream_t st, int64_t n, int64_t nnz, int s, const int64_t* r
   const int sh = lanes_shift(s);
   const int64_t threads = n << sh;
   const int64_t blocks = (threads + 255) / 256;
-  if (tm) tm->begin(st, KK_SPMM);
-  spmm_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(n, s, sh, rp, ci, val, X, W, ctl);
-  if (tm)
-    tm->end(st, KK_SPMM,
-            (double)nnz * (sizeof(T) + sizeof(int)) + 8.0 * (n + 1) + 2.0 * n * s * sizeof(T));
+  const double bytes =
+      (double)nnz * (sizeof(T) + sizeof(int)) + 8.0 * (n + 1) + 2.0 * n * s * sizeof(T);
+  launch_k(tm, KK_SPMM, bytes, spmm_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, n, s, sh,
+           rp, ci, val, X, W, ctl);
 }
 template void launch_spmm<double>(hipStream_t, int64_t, int64_t, int, const int64_t*, const int*,
                                   const double*, const double*, double*, const Ctl*, KTimer*);

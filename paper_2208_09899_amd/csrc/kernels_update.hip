@@ -269,37 +269,40 @@ __global__ __launch_bounds__(256) void update_mfma8(UpdateArgs<double> a, const 
 }
 
 template <typename T, int S>
-void launch_s(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey) {
+void launch_s(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey, KTimer* tm,
+              double bytes) {
   const int64_t blocks = (a.n + 255) / 256;
+  const int ob = obey ? 1 : 0;
   // coefficients in LDS for s <= 8 (at most (3 + 2 (m+1)) s^2 elements, 34 KiB
   // for s = 8, m = 30); larger s reads them through the scalar cache
   if constexpr (sizeof(T) == sizeof(double) && S == 8) {
     if (a.s == 8) {
-      const int64_t blocks4 = (a.n + 63) / 64;
+      const dim3 g((unsigned)((a.n + 63) / 64));
       if (a.has_D)
-        update_mfma8<true><<<dim3((unsigned)blocks4), dim3(256), 0, st>>>(a, ctl, obey ? 1 : 0);
+        launch_k(tm, KK_UPDATE, bytes, update_mfma8<true>, g, dim3(256), 0, st, a, ctl, ob);
       else
-        update_mfma8<false><<<dim3((unsigned)blocks4), dim3(256), 0, st>>>(a, ctl, obey ? 1 : 0);
+        launch_k(tm, KK_UPDATE, bytes, update_mfma8<false>, g, dim3(256), 0, st, a, ctl, ob);
       return;
     }
   }
   // LDS staging covers the coefficients up to D (the folded ones are not read here)
   const size_t coef_bytes = (size_t)(a.lay.D() + a.s * a.s) * sizeof(T);
   const bool lds = S <= 8 && coef_bytes <= 64 * 1024;
+  const dim3 g((unsigned)blocks);
   if (a.s == S) {
     if (lds)
-      update_kernel<T, S, true, true><<<dim3((unsigned)blocks), dim3(256), coef_bytes, st>>>(
-          a, ctl, obey ? 1 : 0);
+      launch_k(tm, KK_UPDATE, bytes, update_kernel<T, S, true, true>, g, dim3(256), coef_bytes,
+               st, a, ctl, ob);
     else
-      update_kernel<T, S, true, false><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(
-          a, ctl, obey ? 1 : 0);
+      launch_k(tm, KK_UPDATE, bytes, update_kernel<T, S, true, false>, g, dim3(256), 0, st, a,
+               ctl, ob);
   } else {
     if (lds)
-      update_kernel<T, S, false, true><<<dim3((unsigned)blocks), dim3(256), coef_bytes, st>>>(
-          a, ctl, obey ? 1 : 0);
+      launch_k(tm, KK_UPDATE, bytes, update_kernel<T, S, false, true>, g, dim3(256), coef_bytes,
+               st, a, ctl, ob);
     else
-      update_kernel<T, S, false, false><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(
-          a, ctl, obey ? 1 : 0);
+      launch_k(tm, KK_UPDATE, bytes, update_kernel<T, S, false, false>, g, dim3(256), 0, st, a,
+               ctl, ob);
   }
 }
 
@@ -322,14 +325,15 @@ template double update_bytes<float>(const UpdateArgs<float>&, int, int, int);
 template <typename T>
 void launch_update(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey_stop,
                    KTimer* tm) {
-  if (tm) tm->begin(st, KK_UPDATE);
-  if (a.s <= 1) launch_s<T, 1>(st, a, ctl, obey_stop);
-  else if (a.s <= 2) launch_s<T, 2>(st, a, ctl, obey_stop);
-  else if (a.s <= 4) launch_s<T, 4>(st, a, ctl, obey_stop);
-  else if (a.s <= 8) launch_s<T, 8>(st, a, ctl, obey_stop);
-  else if (a.s <= 16) launch_s<T, 16>(st, a, ctl, obey_stop);
-  else launch_s<T, 32>(st, a, ctl, obey_stop);
-  if (tm) tm->end(st, KK_UPDATE, a.nvp ? -1.0 : update_bytes(a, a.nv1, a.nv2_begin, a.nv2));
+  // a launch whose block ranges are read on the device gets its bytes once
+  // the host knows them
+  const double bytes = a.nvp ? -1.0 : update_bytes(a, a.nv1, a.nv2_begin, a.nv2);
+  if (a.s <= 1) launch_s<T, 1>(st, a, ctl, obey_stop, tm, bytes);
+  else if (a.s <= 2) launch_s<T, 2>(st, a, ctl, obey_stop, tm, bytes);
+  else if (a.s <= 4) launch_s<T, 4>(st, a, ctl, obey_stop, tm, bytes);
+  else if (a.s <= 8) launch_s<T, 8>(st, a, ctl, obey_stop, tm, bytes);
+  else if (a.s <= 16) launch_s<T, 16>(st, a, ctl, obey_stop, tm, bytes);
+  else launch_s<T, 32>(st, a, ctl, obey_stop, tm, bytes);
 }
 template void launch_update<double>(hipStream_t, const UpdateArgs<double>&, const Ctl*, bool,
                                     KTimer*);

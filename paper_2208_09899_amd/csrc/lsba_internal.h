@@ -8,6 +8,7 @@
 //   small dense     FP64, row-major, in global memory (see Dense below).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -122,8 +123,27 @@ enum KernelKind : int {
 struct KTimer {
   virtual void begin(hipStream_t st, int kind) = 0;
   virtual void end(hipStream_t st, int kind, double bytes) = 0;
+  // Two events that a launch of class `kind` records itself at the start and
+  // the end of the kernel (hipExtLaunchKernelGGL), so that their interval is
+  // the kernel's own duration; false when the class is not timed.
+  virtual bool kernel_events(int kind, hipEvent_t* a, hipEvent_t* b) = 0;
+  virtual void kernel_done(int kind, hipEvent_t a, hipEvent_t b, double bytes) = 0;
   virtual ~KTimer() {}
 };
+
+// Launch `kernel` on st; when tm times class `kind`, the launch records the
+// class's events at the kernel's own start and end.
+template <typename F, typename... Args>
+inline void launch_k(KTimer* tm, int kind, double bytes, F kernel, dim3 grid, dim3 block,
+                     size_t shmem, hipStream_t st, Args... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (tm && tm->kernel_events(kind, &a, &b)) {
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shmem, st, a, b, 0, args...);
+    tm->kernel_done(kind, a, b, bytes);
+  } else {
+    kernel<<<grid, block, shmem, st>>>(args...);
+  }
+}
 
 // ------------------------------------------------------------------ kernels
 // Sparse: W = A X (CSR x row-major block).

@@ -146,6 +146,16 @@ struct EventTimer final : KTimer {
     HIPCHK(hipEventRecord(b, st));
     recs.push_back({kind, bytes, pending, b, step, phase});
   }
+  bool kernel_events(int kind, hipEvent_t* a, hipEvent_t* b) override {
+    if (!on(kind)) return false;
+    *a = take();
+    *b = take();
+    return true;
+  }
+  void kernel_done(int kind, hipEvent_t a, hipEvent_t b, double bytes) override {
+    HIPCHK(hipGetLastError());
+    recs.push_back({kind, bytes, a, b, step, phase});
+  }
   void tag(int st, int ph) {
     step = st;
     phase = ph;
