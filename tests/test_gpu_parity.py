@@ -47,11 +47,14 @@ def test_convdiff_ragged_block_sizes(skel, s):
 
 
 @pytest.mark.parametrize("method", ["fom", "gmres"])
-def test_block_size_32_fom_gmres(method):
+@pytest.mark.parametrize("skel", ["bcgsi_ls", "bmgs_cwy", "bmgs_icwy"])
+def test_block_size_32_fom_gmres(method, skel):
+    """The largest block size: s^2 = 1024 entries per small block, four per
+    thread in the row-split and register-resident small steps."""
     A = w.laplace_3d(12)
     B = w.rhs(A.n, 32, 5)
-    g = gpu_solve(A, B, method=method, skeleton="bcgsi_ls", m=8, tol=1e-10, max_cycles=100)
-    o = oracle_solve(A, B, method, "bcgsi_ls", m=8, tol=1e-10, max_cycles=100)
+    g = gpu_solve(A, B, method=method, skeleton=skel, m=8, tol=1e-10, max_cycles=100)
+    o = oracle_solve(A, B, method, skel, m=8, tol=1e-10, max_cycles=100)
     assert_parity(g, o)
 
 
