@@ -100,7 +100,8 @@ typedef struct {
   int32_t max_cycles;         /* restart cycles allowed                                    */
   int64_t max_iters;          /* total block columns allowed (<= 0: unlimited)             */
   int32_t max_refine;         /* LSBA_MIXED: outer refinement steps allowed                */
-  double inner_tol;           /* LSBA_MIXED: relative tolerance of each inner solve        */
+  double inner_tol;           /* LSBA_MIXED: relative tolerance of each inner solve, loosened
+                                 so that no inner solve aims below tol / 2 overall          */
   uint32_t record;            /* LSBA_REC_* bit set                                        */
   int32_t force_flag_cycle;   /* test hook: raise the Cholesky flag at this cycle (1-based) */
   int32_t force_flag_step;    /*   ... and this skeleton loop step k (0 = first IntraOrtho);

@@ -1332,7 +1332,10 @@ lsba_status lsba_solve(lsba_context* c, const lsba_operator* op, const lsba_para
           break;
         }
         launch_cast<float>(st, n * s, R64, Rf);
-        CycleOut o = run_cycles<float>(c, op, p, k, op->val32, Rf, Df, rn, p.inner_tol, r);
+        // each inner solve reduces its residual by inner_tol, but never further
+        // than the outer target needs (half of it, for the FP32 estimate's slack)
+        const double itol = std::max(p.inner_tol, 0.5 * p.tol * nB / rn);
+        CycleOut o = run_cycles<float>(c, op, p, k, op->val32, Rf, Df, rn, itol, r);
         r->iters += o.iters;
         r->a += o.a;
         r->v += o.v;
