@@ -195,8 +195,8 @@ def main():
                     help="do not record per-kernel HIP events in the timed region")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (got --gpus {args.gpus}); "
+              "sharding a solve across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
