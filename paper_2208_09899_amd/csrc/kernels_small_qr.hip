@@ -21,7 +21,14 @@ __global__ __launch_bounds__(NT) void small_side_kernel(Dense d, int k, int m) {
   {
     const int st = ctl->status;
     if (st == ST_CONVERGED || st == ST_ITERCAP) return;
-    if (st == ST_FLAGGED && ctl->flag_step <= k) return;
+    // A flag raised at a loop step <= k was raised by a kernel this one is
+    // stream-ordered after, so its flag_step is visible here.  A flag raised
+    // concurrently (by a basis-path kernel of a later step) may show its
+    // status before its flag_step; whatever value is read then lies outside
+    // [0, k], and column k - 1 is still final under that flag, so the step
+    // must run.
+    const int fs = ctl->flag_step;
+    if (fs >= 0 && fs <= k) return;
   }
   const int s = d.s, ld = d.ldh, ss = s * s;
   const bool last = (k == m + 1);

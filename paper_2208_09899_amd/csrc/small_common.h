@@ -716,7 +716,12 @@ __device__ __forceinline__ void bcopy(const double* __restrict__ src, double* __
 }
 
 // Raise the Cholesky flag at loop step k; `last_valid` is the last block
-// column that is final.  A convergence already recorded is kept.
+// column that is final.  A convergence already recorded is kept.  The status
+// is published before flag_step / last_valid: a kernel on another stream may
+// see FLAGGED with the cycle-start values (-1, 1 << 30).  Readers therefore
+// trust only values that a flag at a step they are ordered after can write
+// (small_side_kernel: 0 <= flag_step <= k; small_finalize_kernel: a column
+// past last_valid), and such a flag is always fully visible to them.
 __device__ void raise_flag(Ctl* ctl, int k, int last_valid) {
   if (atomicCAS(&ctl->status, (int)ST_RUNNING, (int)ST_FLAGGED) == (int)ST_RUNNING) {
     ctl->flag_step = k;
