@@ -78,9 +78,10 @@ typedef enum { LSBA_CHOLQR = 0, LSBA_HOUSEQR = 1 } lsba_muscle;
 
 typedef enum {
   LSBA_FP64 = 0,              /* every step in FP64                                        */
-  LSBA_MIXED = 1              /* FP32 sparse/Gram/projection products (BF16-input MFMA with
-                                 FP32 accumulation for the Gram at s >= 16), FP64 Cholesky and
-                                 Hessenberg steps, FP64 outer iterative refinement           */
+  LSBA_MIXED = 1              /* inner solves with an FP32 basis: FP32 SpMM, Gram products
+                                 (FP32 products, FP64 cross-lane sums) and projections on the
+                                 vector units; FP64 Cholesky (shifted retry) and Hessenberg
+                                 steps; FP64 outer iterative refinement on B - A X            */
 } lsba_precision;
 
 enum {
@@ -152,6 +153,11 @@ lsba_status lsba_context_set_timing(lsba_context* ctx, uint32_t kind_mask);
  * kernel class since timing was enabled (all zero when disabled). */
 lsba_status lsba_context_kernel_stats(const lsba_context* ctx, int32_t kind, int64_t* launches,
                                       double* total_ms, double* total_bytes);
+/* Summed algorithmic floating-point operations of a kernel class's timed
+ * launches (2 per multiply-add of the products the method needs: the Gram
+ * 2 n (p s)(q s), an update 2 n s^2 per coefficient block it applies, the
+ * SpMM 2 nnz s; 0 for the other classes). */
+lsba_status lsba_context_kernel_flops(const lsba_context* ctx, int32_t kind, double* total_flops);
 
 /* Cycle replay.  A cycle's launch sequence depends only on host values fixed
  * for a solve (buffer and operator pointers, sizes, method, skeleton, muscle,
@@ -170,6 +176,9 @@ lsba_status lsba_context_set_graphs(lsba_context* ctx, int enable);
 lsba_status lsba_operator_create_csr(lsba_context* ctx, int64_t n, int64_t nnz,
                                      const int64_t* row_ptr, const int32_t* col_idx,
                                      const double* values, int on_device, lsba_operator** op);
+/* Free an operator.  Destroying its context first is allowed: the context
+ * then releases the operator's device memory, and this call only frees the
+ * handle. */
 void lsba_operator_destroy(lsba_operator* op);
 
 /* Solve A X = B from X_0 = 0 (eq. Xm).  B and X are n x s row-major with

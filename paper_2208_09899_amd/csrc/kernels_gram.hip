@@ -234,13 +234,187 @@ __global__ __launch_bounds__(256) void gram_mfma_f64(GramArgs<double> a, int nch
   }
 }
 
+// FP64 matrix-core Gram for block sizes that are multiples of 16 (s = 16,
+// 32): a wavefront owns up to SW (4, 5 or 6) left strips of 16 columns against
+// all NTR right tiles of 16 columns (v_mfma_f64_16x16x4f64 tiles, 4 SW NTR
+// accumulator doubles per lane) for a chunk of rows; the waves of a
+// workgroup share the chunk and differ in their strips.  Each wave loads its
+// left fragments itself (one double per lane and strip per group of four
+// rows: four rows x 128 contiguous bytes), four groups of rows ahead.  The
+// right rows, which every wave needs, are staged once per workgroup in LDS,
+// sixteen rows at a time (16-byte loads of whole rows, the next stage in
+// flight in registers, two LDS buffers; row stride padded by 128 bytes so
+// the four rows of a fragment fall in distinct bank halves), and each wave
+// reads its right fragments from there.  So a group of rows costs about one
+// global load instruction per strip, and each right row is fetched from
+// HBM once per chunk.  Partials go to partial[chunk] in the layout of the
+// other stage-1 kernels.  (Measured on MI355X: the 4x4x4 FP64 instruction
+// issues at twice this one's rate, but a 4x4x4 form of this kernel, and one
+// staging every block in LDS, ran no faster: at these shapes the kernel is
+// bound by its memory access, not by the matrix cores.)
+constexpr int kWTR = 16;              // rows per right-operand stage
+constexpr int kWQB = 64;              // largest right width (two blocks of 32)
+constexpr int kWLD = kWQB + 16;       // LDS row stride of a stage (doubles)
+
+template <int SW, int NTR, int RPT>
+__global__ __launch_bounds__(512) void gram_mfma_wide(GramArgs<double> a, int nchunk, int ngroup,
+                                                      int wpg, int64_t rows_per_chunk,
+                                                      double* __restrict__ partial,
+                                                      const Ctl* __restrict__ ctl) {
+  __shared__ double rs[2][kWTR * kWLD];
+  if (ctl && ctl->stop) return;
+  const int pid = blockIdx.x;
+  const int xcd = pid % kXcds, t = pid / kXcds;
+  const int chunk = xcd + kXcds * (t / ngroup);
+  const int grp = t % ngroup;
+  if (chunk >= nchunk) return;
+  const int s = a.s;
+  const int PA = (a.nv + a.nxl) * s, QB = a.nxr * s;
+  const int NS = PA >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  // the chunk's ngroup * wpg wavefronts split the NS strips as evenly as
+  // possible (counts differ by at most one, the larger counts first)
+  const int nw = ngroup * wpg, w = grp * wpg + wave;
+  const int base = NS / nw, extra = NS % nw;
+  const int st0 = w * base + (w < extra ? w : extra);
+  const int nsw = base + (w < extra ? 1 : 0);
+  const int lr = lane & 15, lk = lane >> 4;
+  // strip base pointers are the same for every lane (a strip never
+  // straddles two blocks); the lane's column adds lr
+  const double* Lp[SW];
+#pragma unroll
+  for (int i = 0; i < SW; ++i) {
+    const int col = (st0 + (i < nsw ? i : (nsw > 0 ? nsw - 1 : 0))) * 16;
+    Lp[i] = left_ptr(a, (col < PA ? col : 0) / s) + (col % s) + lr;
+  }
+  const int64_t r0 = (int64_t)chunk * rows_per_chunk;
+  const int64_t r1 = r0 + rows_per_chunk < a.n ? r0 + rows_per_chunk : a.n;
+  const int nst = (int)((r1 - r0 + kWTR - 1) / kWTR);
+  // right-stage staging: 16-byte chunk e = threadIdx.x + blockDim.x u of the
+  // stage is (row e / cpr, chunk e % cpr); RPT >= chunks per thread
+  const int cpr = QB >> 1;                      // chunks per right row
+  const int nchk = kWTR * cpr;
+  typedef double wd2 __attribute__((ext_vector_type(2)));
+  wd2 rreg[RPT];
+  auto rload = [&](int st) {
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int e = threadIdx.x + blockDim.x * u;
+      if (e < nchk) {
+        const int row = e / cpr, col = 2 * (e % cpr);
+        const int64_t grow = r0 + (int64_t)st * kWTR + row;
+        const bool ok = grow < r1;
+        const wd2 v = *reinterpret_cast<const wd2*>(a.xr[col / s] + (col % s) +
+                                                    (ok ? grow : r1 - 1) * s);
+        rreg[u] = ok ? v : wd2{0.0, 0.0};   // rows past r1 contribute 0
+      }
+    }
+  };
+  auto rstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int e = threadIdx.x + blockDim.x * u;
+      if (e < nchk)
+        *reinterpret_cast<wd2*>(&rs[buf][(e / cpr) * kWLD + 2 * (e % cpr)]) = rreg[u];
+    }
+  };
+  // left fragments of the four row groups of a stage (slot kq)
+  double av[4][SW];
+  auto lload = [&](int st, int kq) {
+    const int64_t row = r0 + (int64_t)st * kWTR + 4 * kq + lk;
+    const int64_t off = (row < r1 ? row : r1 - 1) * s;
+#pragma unroll
+    for (int i = 0; i < SW; ++i)
+      if (i < nsw) av[kq][i] = Lp[i][off];
+  };
+  gd4 acc[SW][NTR];
+#pragma unroll
+  for (int i = 0; i < SW; ++i)
+#pragma unroll
+    for (int j = 0; j < NTR; ++j) acc[i][j] = gd4{0.0, 0.0, 0.0, 0.0};
+  if (nst > 0) {
+    rload(0);
+    rstore(0);
+    if (nst > 1) rload(1);
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) lload(0, kq);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const double* R = rs[st & 1];
+    const bool more = st + 1 < nst;
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) {
+      double bv[NTR];
+#pragma unroll
+      for (int j = 0; j < NTR; ++j) bv[j] = R[(4 * kq + lk) * kWLD + 16 * j + lr];
+#pragma unroll
+      for (int i = 0; i < SW; ++i)
+        if (i < nsw)
+#pragma unroll
+          for (int j = 0; j < NTR; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kq][i], bv[j], acc[i][j], 0, 0, 0);
+      if (more) lload(st + 1, kq);
+    }
+    if (more) {
+      rstore((st + 1) & 1);
+      if (st + 2 < nst) rload(st + 2);
+    }
+    __syncthreads();
+  }
+  double* out = partial + (int64_t)chunk * PA * QB;
+#pragma unroll
+  for (int i = 0; i < SW; ++i)
+    if (i < nsw)
+#pragma unroll
+      for (int j = 0; j < NTR; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          out[(int64_t)((st0 + i) * 16 + 4 * q + lk) * QB + j * 16 + lr] = acc[i][j][q];
+}
+
 struct MPlan {
   int nchunk, ngroup;
   int64_t rows;
 };
 
-// About 2048 workgroups (eight resident waves per SIMD), chunks of at least
-// 256 rows.
+// Plan of gram_mfma_wide: the row chunk's strips are split over nw
+// wavefronts: one per strip while NS <= 4, 4 * ceil(NS / 16) (at most 4
+// strips each) while NS <= 16, else 8 per 40 strips (at most 5 each, four
+// right tiles) or per 48 strips (at most 6 each, fewer tiles), so that for
+// the shapes of a restart cycle one workgroup stages each right row once; 8
+// wavefronts per workgroup when that divides nw, else 4 (or nw); enough row
+// chunks for about 2048 busy wavefronts (at least 256 rows each, a multiple
+// of 16).
+struct WPlan {
+  int ntr, sw, wpg, ngroup, nchunk;
+  int64_t rows;
+};
+
+bool use_wide(int s, int QB) { return s % 16 == 0 && (QB == 16 || QB == 32 || QB == 64); }
+
+WPlan wplan(int64_t n, int PA, int QB) {
+  WPlan p;
+  p.ntr = QB / 16;
+  const int ns = PA / 16;
+  // above 16 strips: 8 wavefronts per 40 (NTR = 4, at most 5 each) or per
+  // 48 strips (at most 6 each)
+  const int big = p.ntr == 4 ? 5 : 6;
+  const int nw = ns <= 4 ? ns : (ns <= 16 ? 4 * ((ns + 15) / 16) : 8 * ((ns + 8 * big - 1) / (8 * big)));
+  p.sw = ns <= 16 ? 4 : big;
+  p.wpg = nw % 8 == 0 ? 8 : (nw % 4 == 0 ? 4 : nw);
+  p.ngroup = nw / p.wpg;
+  int64_t nchunk = 2048 / nw;
+  const int64_t maxc = (n + 255) / 256;
+  if (nchunk > maxc) nchunk = maxc;
+  if (nchunk < 1) nchunk = 1;
+  p.rows = (((n + nchunk - 1) / nchunk) + 15) & ~int64_t(15);
+  p.nchunk = (int)((n + p.rows - 1) / p.rows);
+  return p;
+}
+
+// Plan of gram_mfma_f64: about 2048 workgroups (eight resident waves per
+// SIMD), chunks of at least 256 rows.
 MPlan mplan(int64_t n, int PA, int QB) {
   MPlan p;
   const int ntile = ((PA + 15) / 16) * ((QB + 15) / 16);
@@ -297,6 +471,11 @@ size_t gram_partial_doubles(int64_t n, int s, int nleft, int nright) {
         const size_t nm = (size_t)q.nchunk * (size_t)(nl * s) * (size_t)(nr * s);
         if (nm > need) need = nm;
       }
+      if (use_wide(s, nr * s)) {
+        const WPlan q = wplan(n, nl * s, nr * s);
+        const size_t nm = (size_t)q.nchunk * (size_t)(nl * s) * (size_t)(nr * s);
+        if (nm > need) need = nm;
+      }
       if (need > best) best = need;
     }
   return best;
@@ -330,11 +509,33 @@ template <typename T>
 void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* out,
                  const Ctl* ctl, KTimer* tm) {
   const int PA = (a.nv + a.nxl) * a.s, QB = a.nxr * a.s;
+  const double gflops = 2.0 * (double)a.n * PA * QB;
   if constexpr (sizeof(T) == sizeof(double)) {
+    if (use_wide(a.s, QB)) {
+      const WPlan q = wplan(a.n, PA, QB);
+      const int nchunk_pad = ((q.nchunk + kXcds - 1) / kXcds) * kXcds;
+      const dim3 g(nchunk_pad * q.ngroup), b(64 * q.wpg);
+      const double bytes = (double)distinct_blocks(a) * a.n * a.s * sizeof(T);
+#define LSBA_WIDE(SW, NTR)                                                                   \
+  launch_kf(tm, KK_GRAM, bytes, gflops, gram_mfma_wide<SW, NTR, (SW > 4 ? 1 : 8)>, g, b, 0,          \
+           st, a, q.nchunk, q.ngroup, q.wpg, q.rows, partial, ctl)
+      if (q.sw == 4) {
+        if (q.ntr == 4) LSBA_WIDE(4, 4);
+        else if (q.ntr == 2) LSBA_WIDE(4, 2);
+        else LSBA_WIDE(4, 1);
+      } else {
+        if (q.ntr == 4) LSBA_WIDE(5, 4);
+        else if (q.ntr == 2) LSBA_WIDE(6, 2);
+        else LSBA_WIDE(6, 1);
+      }
+#undef LSBA_WIDE
+      launch_stage2(st, partial, q.nchunk, PA * QB, out, ctl, tm);
+      return;
+    }
     if (use_mfma(a.s)) {
       const MPlan q = mplan(a.n, PA, QB);
       const int nchunk_pad = ((q.nchunk + kXcds - 1) / kXcds) * kXcds;
-      launch_k(tm, KK_GRAM, (double)distinct_blocks(a) * a.n * a.s * sizeof(T), gram_mfma_f64,
+      launch_kf(tm, KK_GRAM, (double)distinct_blocks(a) * a.n * a.s * sizeof(T), gflops, gram_mfma_f64,
                dim3(nchunk_pad * q.ngroup), dim3(256), 0, st, a, q.nchunk, q.ngroup, q.rows,
                partial, ctl);
       launch_stage2(st, partial, q.nchunk, PA * QB, out, ctl, tm);
@@ -347,19 +548,19 @@ void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* 
   const double bytes = (double)distinct_blocks(a) * a.n * a.s * sizeof(T);
   switch (p.tl) {
     case 8:
-      launch_k(tm, KK_GRAM, bytes, gram_stage1<T, 8>, dim3(blocks), dim3(256), 0, st, a, p.nchunk,
+      launch_kf(tm, KK_GRAM, bytes, gflops, gram_stage1<T, 8>, dim3(blocks), dim3(256), 0, st, a, p.nchunk,
                p.ngroup, p.rows, partial, ctl);
       break;
     case 4:
-      launch_k(tm, KK_GRAM, bytes, gram_stage1<T, 4>, dim3(blocks), dim3(256), 0, st, a, p.nchunk,
+      launch_kf(tm, KK_GRAM, bytes, gflops, gram_stage1<T, 4>, dim3(blocks), dim3(256), 0, st, a, p.nchunk,
                p.ngroup, p.rows, partial, ctl);
       break;
     case 2:
-      launch_k(tm, KK_GRAM, bytes, gram_stage1<T, 2>, dim3(blocks), dim3(256), 0, st, a, p.nchunk,
+      launch_kf(tm, KK_GRAM, bytes, gflops, gram_stage1<T, 2>, dim3(blocks), dim3(256), 0, st, a, p.nchunk,
                p.ngroup, p.rows, partial, ctl);
       break;
     default:
-      launch_k(tm, KK_GRAM, bytes, gram_stage1<T, 1>, dim3(blocks), dim3(256), 0, st, a, p.nchunk,
+      launch_kf(tm, KK_GRAM, bytes, gflops, gram_stage1<T, 1>, dim3(blocks), dim3(256), 0, st, a, p.nchunk,
                p.ngroup, p.rows, partial, ctl);
   }
   launch_stage2(st, partial, p.nchunk, PA * QB, out, ctl, tm);

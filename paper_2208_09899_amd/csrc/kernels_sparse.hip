@@ -36,6 +36,56 @@ __global__ __launch_bounds__(256) void spmm_kernel(int64_t n, int s, int lshift,
   W[row * s + c] = acc;
 }
 
+// Cooperative variant for L >= 8 lanes per row: the L lanes of a row first
+// load up to L of the row's (column, value) pairs at once (lane c takes
+// entry c of the round), then walk them, receiving each pair by a cross-lane
+// shuffle, with the gathers of eight entries in flight before their products
+// are added in entry order.  The gather addresses are known one load after
+// the row pointer instead of one dependent load per entry.  Workgroups are
+// renumbered so that each XCD takes a contiguous range of rows, whose
+// neighbours' gathers then hit that XCD's L2.
+constexpr int kXcdsSp = 8;
+
+template <typename T, int L>
+__global__ __launch_bounds__(256) void spmm_coop_kernel(int64_t n, int s, int64_t nblk,
+                                                        int64_t per_xcd,
+                                                        const int64_t* __restrict__ rp,
+                                                        const int* __restrict__ ci,
+                                                        const T* __restrict__ val,
+                                                        const T* __restrict__ X,
+                                                        T* __restrict__ W,
+                                                        const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->stop) return;
+  constexpr int RPB = 256 / L;   // rows per workgroup
+  const int64_t blk = (int64_t)(blockIdx.x % kXcdsSp) * per_xcd + blockIdx.x / kXcdsSp;
+  if (blk >= nblk) return;
+  const int64_t row = blk * RPB + threadIdx.x / L;
+  const int c = threadIdx.x & (L - 1);
+  if (row >= n) return;   // whole groups of L lanes leave together
+  const int64_t b = rp[row], e = rp[row + 1];
+  T acc = T(0);
+  const bool col_ok = c < s;
+  for (int64_t base = b; base < e; base += L) {
+    const int cnt = e - base < L ? (int)(e - base) : L;
+    const int my_ci = c < cnt ? ci[base + c] : 0;
+    const T my_v = c < cnt ? val[base + c] : T(0);
+    for (int j = 0; j < cnt; j += 8) {
+      T xv[8], vv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int jj = j + u;
+        const int cc = __shfl(my_ci, jj & (L - 1), L);
+        vv[u] = __shfl(my_v, jj & (L - 1), L);
+        xv[u] = (jj < cnt && col_ok) ? X[(int64_t)cc * s + c] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j + u < cnt) acc += vv[u] * xv[u];
+    }
+  }
+  if (col_ok) W[row * s + c] = acc;
+}
+
 // Sum of a value across the workgroup (256 threads), fixed tree order.
 __device__ double block_sum_256(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -118,7 +168,21 @@ void launch_spmm(hipStream_t st, int64_t n, int64_t nnz, int s, const int64_t* r
   const int64_t blocks = (threads + 255) / 256;
   const double bytes =
       (double)nnz * (sizeof(T) + sizeof(int)) + 8.0 * (n + 1) + 2.0 * n * s * sizeof(T);
-  launch_k(tm, KK_SPMM, bytes, spmm_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, n, s, sh,
+  if (sh >= 3) {
+    const int64_t per_xcd = (blocks + kXcdsSp - 1) / kXcdsSp;
+    const dim3 g((unsigned)(per_xcd * kXcdsSp));
+    if (sh == 3)
+      launch_kf(tm, KK_SPMM, bytes, 2.0 * (double)nnz * s, spmm_coop_kernel<T, 8>, g, dim3(256), 0, st, n, s, blocks,
+               per_xcd, rp, ci, val, X, W, ctl);
+    else if (sh == 4)
+      launch_kf(tm, KK_SPMM, bytes, 2.0 * (double)nnz * s, spmm_coop_kernel<T, 16>, g, dim3(256), 0, st, n, s, blocks,
+               per_xcd, rp, ci, val, X, W, ctl);
+    else
+      launch_kf(tm, KK_SPMM, bytes, 2.0 * (double)nnz * s, spmm_coop_kernel<T, 32>, g, dim3(256), 0, st, n, s, blocks,
+               per_xcd, rp, ci, val, X, W, ctl);
+    return;
+  }
+  launch_kf(tm, KK_SPMM, bytes, 2.0 * (double)nnz * s, spmm_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, n, s, sh,
            rp, ci, val, X, W, ctl);
 }
 template void launch_spmm<double>(hipStream_t, int64_t, int64_t, int, const int64_t*, const int*,

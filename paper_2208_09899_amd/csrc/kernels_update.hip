@@ -268,9 +268,182 @@ __global__ __launch_bounds__(256) void update_mfma8(UpdateArgs<double> a, const 
   }
 }
 
+// FP64, s = 16 or 32, on the matrix cores: [out1 | out2] (2s columns, NT
+// tiles of 16) is the product of the input rows [in1 | V_i ... | in2] with
+// the stacked coefficient rows, as in update_mfma8.  A workgroup of 8
+// wavefronts owns 256 consecutive rows (RG groups of 16 rows per wavefront)
+// and walks the inputs in order; for each input the coefficient fragments
+// of all its K-steps and output tiles (8 x 4 x 64 doubles for s = 32) are
+// staged in LDS once per workgroup, double-buffered, so each wavefront
+// reads them conflict-free (lane l reads word l) instead of from L2.  The K
+// index of a product may be permuted freely as long as both operands use
+// the same order: lane l = (r, q) (row r = l % 16, q = l / 16) loads the
+// 16-byte chunks q, q + 4, ... of its row (a wavefront's load covers 16
+// rows x 64 contiguous bytes) and K-step h takes column
+// c(h, q) = 2q + (h & 1) + 8 (h >> 1) of that row; the coefficient fragment
+// of step h holds coefficient row c(h, l / 16).  The next input's rows and
+// coefficients are loaded while the current one is multiplied.  Every
+// output row depends on its own input rows only, so rows past n read a
+// valid row and are not written.  (The 4x4x4 FP64 instruction issues at
+// twice the rate on gfx950 but needs the row operand replicated in four
+// lanes; measured here, that version of this kernel was 1.75x slower.)
+constexpr int kWideRG = 2;
+
+__device__ __forceinline__ int wide_kcol(int h, int q) { return 2 * q + (h & 1) + 8 * (h >> 1); }
+
+template <int S, bool FOLD>
+__global__ __launch_bounds__(512) void update_mfma_wide(UpdateArgs<double> a,
+                                                        const Ctl* __restrict__ ctl,
+                                                        int obey_stop) {
+  constexpr int NT = 2 * S / 16;    // output tiles of 16 columns
+  constexpr int KS = S / 4;         // K-steps per input block
+  constexpr int NCH = S / 8;        // 16-byte chunks per lane and row
+  constexpr int RG = kWideRG;
+  constexpr int FR = KS * NT * 64;  // doubles of one input's coefficient fragments
+  __shared__ double cf[2][FR];
+  if (obey_stop && ctl && ctl->stop) return;
+  int nv1 = a.nv1, nb = a.nv2_begin, nv2 = a.nv2;
+  if (a.nvp) {
+    nv1 = a.nvp[0];
+    nb = a.nvp[1];
+    nv2 = a.nvp[2];
+    if (nv1 < 0) return;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int64_t wrow0 = (int64_t)blockIdx.x * (8 * RG * 16) + (int64_t)wave * (RG * 16);
+  const int nvmax = nv1 > nv2 ? nv1 : nv2;
+  InputSeq<double> in;
+  in.in1 = a.in1;
+  in.in2 = a.in2;
+  in.V = a.V;
+  in.off = 0;
+  in.bstride = a.n * S;
+  in.h1 = a.in1 ? 1 : 0;
+  in.i0 = nv1 > 0 ? 0 : nb;
+  if (FOLD && nv1 > 0) in.i0 = 0;
+  in.nbas = nvmax > in.i0 ? nvmax - in.i0 : 0;
+  in.nv1 = nv1;
+  in.nb = nb;
+  in.nv2 = nv2;
+  const int nin = in.h1 + in.nbas + (a.in2 ? 1 : 0);
+  // this lane's row offsets (rows past n read row n - 1)
+  int64_t roff[RG];
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    const int64_t row = wrow0 + 16 * g + lr;
+    roff[g] = (row < a.n ? row : a.n - 1) * S + 2 * lq;
+  }
+  // coefficient fragment entries this thread stages: e = threadIdx.x + 512 u
+  constexpr int CPT = (FR + 511) / 512;
+  auto coef_load = [&](int q, double (&cv)[CPT]) {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int e = threadIdx.x + 512 * u;
+      double v = 0.0;
+      if (e < FR) {
+        const int l = e & 63, tq = e >> 6;
+        const int t = tq % NT, h = tq / NT;
+        const int half = t / (NT / 2);
+        const int col = (t % (NT / 2)) * 16 + (l & 15);
+        const int krow = wide_kcol(h, l >> 4);
+        const double* blk = nullptr;
+        if (q < in.h1) {
+          blk = half ? (FOLD ? a.coef + a.lay.C1D() : nullptr) : a.coef + a.lay.C1();
+        } else if (q - in.h1 < in.nbas) {
+          const int i = in.i0 + q - in.h1;
+          if (!half) blk = i < nv1 ? a.coef + a.lay.A(i) : nullptr;
+          else if (FOLD) blk = a.coef + a.lay.BF(i);
+          else blk = (i >= nb && i < nv2) ? a.coef + a.lay.B(i) : nullptr;
+        } else {
+          blk = half ? a.coef + a.lay.C2() : nullptr;
+        }
+        if (blk) v = blk[krow * S + col];
+      }
+      cv[u] = v;
+    }
+  };
+  auto coef_store = [&](int buf, const double (&cv)[CPT]) {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int e = threadIdx.x + 512 * u;
+      if (e < FR) cf[buf][e] = cv[u];
+    }
+  };
+  typedef double dbl2 __attribute__((ext_vector_type(2)));
+  auto rows_load = [&](int q, dbl2 (&x)[RG][NCH]) {
+    const double* p = in.ptr(q);
+#pragma unroll
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+      for (int j = 0; j < NCH; ++j)
+        x[g][j] = *reinterpret_cast<const dbl2*>(p + roff[g] + 8 * j);
+  };
+  ud4 acc[RG][NT];
+#pragma unroll
+  for (int g = 0; g < RG; ++g)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[g][t] = ud4{0.0, 0.0, 0.0, 0.0};
+  dbl2 xc[RG][NCH], xn[RG][NCH];
+  double cvn[CPT];
+  if (nin > 0) {
+    coef_load(0, cvn);
+    rows_load(0, xc);
+    coef_store(0, cvn);
+  }
+  __syncthreads();
+  for (int q = 0; q < nin; ++q) {
+    const int buf = q & 1;
+    const bool more = q + 1 < nin;
+    if (more) {
+      coef_load(q + 1, cvn);
+      rows_load(q + 1, xn);
+    }
+#pragma unroll
+    for (int h = 0; h < KS; ++h) {
+      double bf[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bf[t] = cf[buf][(h * NT + t) * 64 + lane];
+#pragma unroll
+      for (int g = 0; g < RG; ++g) {
+        const double av = (h & 1) ? xc[g][h >> 1].y : xc[g][h >> 1].x;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc[g][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bf[t], acc[g][t], 0, 0, 0);
+      }
+    }
+    if (more) {
+      coef_store(buf ^ 1, cvn);
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) xc[g][j] = xn[g][j];
+    }
+    __syncthreads();
+  }
+  const bool w2 = a.out2 && (a.in2 || nv2 > nb);
+#pragma unroll
+  for (int g = 0; g < RG; ++g)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = wrow0 + 16 * g + 4 * r + lq;
+      if (row >= a.n) continue;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int half = t / (NT / 2);
+        const int col = (t % (NT / 2)) * 16 + lr;
+        if (!half) {
+          if (a.out1) a.out1[row * S + col] = acc[g][t][r];
+        } else if (w2) {
+          a.out2[row * S + col] = acc[g][t][r];
+        }
+      }
+    }
+}
+
 template <typename T, int S>
 void launch_s(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey, KTimer* tm,
-              double bytes) {
+              double bytes, double flops) {
   const int64_t blocks = (a.n + 255) / 256;
   const int ob = obey ? 1 : 0;
   // coefficients in LDS for s <= 8 (at most (3 + 2 (m+1)) s^2 elements, 34 KiB
@@ -279,9 +452,20 @@ void launch_s(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey,
     if (a.s == 8) {
       const dim3 g((unsigned)((a.n + 63) / 64));
       if (a.has_D)
-        launch_k(tm, KK_UPDATE, bytes, update_mfma8<true>, g, dim3(256), 0, st, a, ctl, ob);
+        launch_kf(tm, KK_UPDATE, bytes, flops, update_mfma8<true>, g, dim3(256), 0, st, a, ctl, ob);
       else
-        launch_k(tm, KK_UPDATE, bytes, update_mfma8<false>, g, dim3(256), 0, st, a, ctl, ob);
+        launch_kf(tm, KK_UPDATE, bytes, flops, update_mfma8<false>, g, dim3(256), 0, st, a, ctl, ob);
+      return;
+    }
+  }
+  if constexpr (sizeof(T) == sizeof(double) && (S == 16 || S == 32)) {
+    if (a.s == S) {
+      const dim3 g((unsigned)((a.n + 8 * kWideRG * 16 - 1) / (8 * kWideRG * 16)));
+      if (a.has_D)
+        launch_kf(tm, KK_UPDATE, bytes, flops, update_mfma_wide<S, true>, g, dim3(512), 0, st, a, ctl, ob);
+      else
+        launch_kf(tm, KK_UPDATE, bytes, flops, update_mfma_wide<S, false>, g, dim3(512), 0, st, a, ctl,
+                 ob);
       return;
     }
   }
@@ -291,17 +475,17 @@ void launch_s(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey,
   const dim3 g((unsigned)blocks);
   if (a.s == S) {
     if (lds)
-      launch_k(tm, KK_UPDATE, bytes, update_kernel<T, S, true, true>, g, dim3(256), coef_bytes,
+      launch_kf(tm, KK_UPDATE, bytes, flops, update_kernel<T, S, true, true>, g, dim3(256), coef_bytes,
                st, a, ctl, ob);
     else
-      launch_k(tm, KK_UPDATE, bytes, update_kernel<T, S, true, false>, g, dim3(256), 0, st, a,
+      launch_kf(tm, KK_UPDATE, bytes, flops, update_kernel<T, S, true, false>, g, dim3(256), 0, st, a,
                ctl, ob);
   } else {
     if (lds)
-      launch_k(tm, KK_UPDATE, bytes, update_kernel<T, S, false, true>, g, dim3(256), coef_bytes,
+      launch_kf(tm, KK_UPDATE, bytes, flops, update_kernel<T, S, false, true>, g, dim3(256), coef_bytes,
                st, a, ctl, ob);
     else
-      launch_k(tm, KK_UPDATE, bytes, update_kernel<T, S, false, false>, g, dim3(256), 0, st, a,
+      launch_kf(tm, KK_UPDATE, bytes, flops, update_kernel<T, S, false, false>, g, dim3(256), 0, st, a,
                ctl, ob);
   }
 }
@@ -323,17 +507,29 @@ template double update_bytes<double>(const UpdateArgs<double>&, int, int, int);
 template double update_bytes<float>(const UpdateArgs<float>&, int, int, int);
 
 template <typename T>
+double update_flops(const UpdateArgs<T>& a, int nv1, int nb, int nv2) {
+  if (nv1 < 0) return 0.0;
+  const bool w2 = a.out2 && (a.in2 || nv2 > nb);
+  int prods = (a.out1 && a.in1 ? 1 : 0) + (a.out1 ? (nv1 > 0 ? nv1 : 0) : 0);
+  if (w2) prods += (a.in2 ? 1 : 0) + (nv2 > nb ? nv2 - nb : 0) + (a.has_D ? 1 : 0);
+  return 2.0 * (double)prods * a.n * a.s * a.s;
+}
+template double update_flops<double>(const UpdateArgs<double>&, int, int, int);
+template double update_flops<float>(const UpdateArgs<float>&, int, int, int);
+
+template <typename T>
 void launch_update(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey_stop,
                    KTimer* tm) {
   // a launch whose block ranges are read on the device gets its bytes once
   // the host knows them
   const double bytes = a.nvp ? -1.0 : update_bytes(a, a.nv1, a.nv2_begin, a.nv2);
-  if (a.s <= 1) launch_s<T, 1>(st, a, ctl, obey_stop, tm, bytes);
-  else if (a.s <= 2) launch_s<T, 2>(st, a, ctl, obey_stop, tm, bytes);
-  else if (a.s <= 4) launch_s<T, 4>(st, a, ctl, obey_stop, tm, bytes);
-  else if (a.s <= 8) launch_s<T, 8>(st, a, ctl, obey_stop, tm, bytes);
-  else if (a.s <= 16) launch_s<T, 16>(st, a, ctl, obey_stop, tm, bytes);
-  else launch_s<T, 32>(st, a, ctl, obey_stop, tm, bytes);
+  const double flops = a.nvp ? 0.0 : update_flops(a, a.nv1, a.nv2_begin, a.nv2);
+  if (a.s <= 1) launch_s<T, 1>(st, a, ctl, obey_stop, tm, bytes, flops);
+  else if (a.s <= 2) launch_s<T, 2>(st, a, ctl, obey_stop, tm, bytes, flops);
+  else if (a.s <= 4) launch_s<T, 4>(st, a, ctl, obey_stop, tm, bytes, flops);
+  else if (a.s <= 8) launch_s<T, 8>(st, a, ctl, obey_stop, tm, bytes, flops);
+  else if (a.s <= 16) launch_s<T, 16>(st, a, ctl, obey_stop, tm, bytes, flops);
+  else launch_s<T, 32>(st, a, ctl, obey_stop, tm, bytes, flops);
 }
 template void launch_update<double>(hipStream_t, const UpdateArgs<double>&, const Ctl*, bool,
                                     KTimer*);

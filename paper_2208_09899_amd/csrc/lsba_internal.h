@@ -127,22 +127,30 @@ struct KTimer {
   // the end of the kernel (hipExtLaunchKernelGGL), so that their interval is
   // the kernel's own duration; false when the class is not timed.
   virtual bool kernel_events(int kind, hipEvent_t* a, hipEvent_t* b) = 0;
-  virtual void kernel_done(int kind, hipEvent_t a, hipEvent_t b, double bytes) = 0;
+  // `flops`: the launch's algorithmic floating-point operations (the
+  // products the method needs, 2 per multiply-add)
+  virtual void kernel_done(int kind, hipEvent_t a, hipEvent_t b, double bytes,
+                           double flops) = 0;
   virtual ~KTimer() {}
 };
 
 // Launch `kernel` on st; when tm times class `kind`, the launch records the
 // class's events at the kernel's own start and end.
 template <typename F, typename... Args>
-inline void launch_k(KTimer* tm, int kind, double bytes, F kernel, dim3 grid, dim3 block,
-                     size_t shmem, hipStream_t st, Args... args) {
+inline void launch_kf(KTimer* tm, int kind, double bytes, double flops, F kernel, dim3 grid,
+                      dim3 block, size_t shmem, hipStream_t st, Args... args) {
   hipEvent_t a = nullptr, b = nullptr;
   if (tm && tm->kernel_events(kind, &a, &b)) {
     hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shmem, st, a, b, 0, args...);
-    tm->kernel_done(kind, a, b, bytes);
+    tm->kernel_done(kind, a, b, bytes, flops);
   } else {
     kernel<<<grid, block, shmem, st>>>(args...);
   }
+}
+template <typename F, typename... Args>
+inline void launch_k(KTimer* tm, int kind, double bytes, F kernel, dim3 grid, dim3 block,
+                     size_t shmem, hipStream_t st, Args... args) {
+  launch_kf(tm, kind, bytes, 0.0, kernel, grid, block, shmem, st, args...);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -195,9 +203,13 @@ struct UpdateArgs {
   const T* coef;
   CoefLayout lay;
 };
-// Algorithmic bytes of one update launch with nv1 / nv2_begin / nv2 block ranges.
+// Algorithmic bytes and flops of one update launch with nv1 / nv2_begin / nv2
+// block ranges (flops: 2 n s^2 per nonzero s x s coefficient block applied,
+// the D term included).
 template <typename T>
 double update_bytes(const UpdateArgs<T>& a, int nv1, int nb, int nv2);
+template <typename T>
+double update_flops(const UpdateArgs<T>& a, int nv1, int nb, int nv2);
 template <typename T>
 void launch_update(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey_stop,
                    KTimer* tm = nullptr);

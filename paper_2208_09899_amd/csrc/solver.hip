@@ -23,6 +23,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <set>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -66,6 +67,10 @@ struct lsba_context {
   std::vector<GraphEnt> graphs;
   uint64_t graph_tick = 0;
   bool graphs_on = false;
+  // live operators of this context: destroying the context releases their
+  // device memory and detaches them, so that a later lsba_operator_destroy
+  // (in any order, e.g. from a garbage collector) never reads a freed context
+  std::set<lsba_operator*> ops;
 };
 
 
@@ -112,10 +117,11 @@ struct EventTimer final : KTimer {
     double bytes;
     hipEvent_t a, b;
     int step, phase;
+    double flops;
   };
   struct Acc {
     int64_t launches = 0;
-    double ms = 0.0, bytes = 0.0;
+    double ms = 0.0, bytes = 0.0, flops = 0.0;
   };
   std::vector<hipEvent_t> pool;
   size_t used = 0;
@@ -144,7 +150,7 @@ struct EventTimer final : KTimer {
     if (!on(kind)) return;
     hipEvent_t b = take();
     HIPCHK(hipEventRecord(b, st));
-    recs.push_back({kind, bytes, pending, b, step, phase});
+    recs.push_back({kind, bytes, pending, b, step, phase, 0.0});
   }
   bool kernel_events(int kind, hipEvent_t* a, hipEvent_t* b) override {
     if (!on(kind)) return false;
@@ -152,9 +158,9 @@ struct EventTimer final : KTimer {
     *b = take();
     return true;
   }
-  void kernel_done(int kind, hipEvent_t a, hipEvent_t b, double bytes) override {
+  void kernel_done(int kind, hipEvent_t a, hipEvent_t b, double bytes, double flops) override {
     HIPCHK(hipGetLastError());
-    recs.push_back({kind, bytes, a, b, step, phase});
+    recs.push_back({kind, bytes, a, b, step, phase, flops});
   }
   void tag(int st, int ph) {
     step = st;
@@ -167,7 +173,10 @@ struct EventTimer final : KTimer {
   // small kernel (phase 1) did not run either.
   void kill_after(int k_stop, bool flagged) {
     for (auto& r : recs)
-      if (r.step > k_stop || (flagged && r.step == k_stop && r.phase == 1)) r.bytes = 0.0;
+      if (r.step > k_stop || (flagged && r.step == k_stop && r.phase == 1)) {
+        r.bytes = 0.0;
+        r.flops = 0.0;
+      }
   }
   void flush() {
     for (auto& r : recs) {
@@ -176,6 +185,7 @@ struct EventTimer final : KTimer {
       acc[r.kind].launches += 1;
       acc[r.kind].ms += ms;
       if (r.bytes > 0) acc[r.kind].bytes += r.bytes;
+      if (r.flops > 0) acc[r.kind].flops += r.flops;
     }
     recs.clear();
     used = 0;
@@ -822,8 +832,10 @@ struct CycleRunner {
     const int cst = hc.cyc_status;
     if (tm) {
       // bytes of the basis application, known only now
-      if (tm->on(KK_UPDATE) && !tm->recs.empty())
+      if (tm->on(KK_UPDATE) && !tm->recs.empty()) {
         tm->recs.back().bytes = update_bytes(uapply, hc.nv1, hc.nv2_begin, hc.nv2);
+        tm->recs.back().flops = update_flops(uapply, hc.nv1, hc.nv2_begin, hc.nv2);
+      }
       if (cst == ST_CONVERGED || cst == ST_ITERCAP)
         tm->kill_after(delayed ? j + 1 : j, false);
       else if (cst == ST_FLAGGED)
@@ -901,11 +913,27 @@ struct SrvSlot {
   bool in_flight = false;
 };
 
-double device_norm(lsba_context* c, const double* x, int64_t count) {
-  double* partial = (double*)ctx_buf(c, "norm_partial", sizeof(double) * ((count / 4096) + 2));
+// Workspaces of the norm / residual reductions: taken from the context's
+// buffer cache unless the caller passes them (the no-allocation entry point).
+struct NormWork {
+  double* norm_partial = nullptr;   // norm_partial_doubles(count)
+  double* res_partial = nullptr;    // res_partial_doubles(n, s)
+  double* out = nullptr;            // 4 doubles
+};
+size_t norm_partial_doubles(int64_t count) { return (size_t)(count / 4096) + 2; }
+size_t res_partial_doubles(int64_t n, int s) {
+  int sh = 0;
+  while ((1 << sh) < s) ++sh;
+  return (size_t)(((n << sh) + 255) / 256) + 1;
+}
+
+double device_norm(lsba_context* c, const double* x, int64_t count, const NormWork* w = nullptr) {
+  double* partial = w ? w->norm_partial
+                      : (double*)ctx_buf(c, "norm_partial",
+                                         sizeof(double) * norm_partial_doubles(count));
   int nw = 0;
   launch_sumsq_partial(c->stream, count, x, partial, &nw);
-  double* outd = (double*)ctx_buf(c, "norm_out", sizeof(double) * 4);
+  double* outd = w ? w->out : (double*)ctx_buf(c, "norm_out", sizeof(double) * 4);
   launch_sumsq_final(c->stream, partial, nw, outd);
   HIPCHK(hipMemcpyAsync(c->norm_host, outd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -914,15 +942,14 @@ double device_norm(lsba_context* c, const double* x, int64_t count) {
 
 // R = B - A X (R may be null) and ||R||_F, FP64.
 double device_residual(lsba_context* c, const lsba_operator* op, int s, const double* X,
-                       const double* B, double* R) {
-  int sh = 0;
-  while ((1 << sh) < s) ++sh;
-  const int64_t blocks = ((op->n << sh) + 255) / 256;
-  double* partial = (double*)ctx_buf(c, "res_partial", sizeof(double) * (blocks + 1));
+                       const double* B, double* R, const NormWork* w = nullptr) {
+  double* partial = w ? w->res_partial
+                      : (double*)ctx_buf(c, "res_partial",
+                                         sizeof(double) * res_partial_doubles(op->n, s));
   int nw = 0;
   launch_residual(c->stream, op->n, op->nnz, s, op->rp, op->ci, op->val, X, B, R, partial, &nw,
                   c->timer);
-  double* outd = (double*)ctx_buf(c, "norm_out", sizeof(double) * 4);
+  double* outd = w ? w->out : (double*)ctx_buf(c, "norm_out", sizeof(double) * 4);
   launch_sumsq_final(c->stream, partial, nw, outd);
   HIPCHK(hipMemcpyAsync(c->norm_host, outd, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -952,6 +979,7 @@ lsba_status fail(lsba_context* c, lsba_status st, const std::string& msg) {
   else g_create_err = msg;
   return st;
 }
+
 
 }  // namespace
 
@@ -1041,7 +1069,10 @@ void srv_progress(lsba_server* sv) {
   for (auto& sl : sv->slots) {
     if (!sl.req || !sl.in_flight) continue;
     const hipError_t q = hipEventQuery(sl.c->ev_done);
-    if (q == hipErrorNotReady) continue;
+    if (q == hipErrorNotReady) {
+      (void)hipGetLastError();   // HIP records "not ready" as the thread's last error
+      continue;
+    }
     if (q != hipSuccess) throw HipError{std::string("cycle event: ") + hipGetErrorString(q)};
     HIPCHK(hipGetLastError());
     sl.in_flight = false;
@@ -1152,8 +1183,7 @@ lsba_status lsba_context_create(int device, void* hip_stream, lsba_context** out
                          hipHostMallocDefault));
     HIPCHK(hipEventCreate(&c->ev0));
     HIPCHK(hipEventCreate(&c->ev1));
-    HIPCHK(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
-  } catch (const HipError& e) {
+    HIPCHK(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));  } catch (const HipError& e) {
     lsba_context_destroy(c);
     return fail(nullptr, LSBA_ERR_HIP, e.msg);
   }
@@ -1161,10 +1191,17 @@ lsba_status lsba_context_create(int device, void* hip_stream, lsba_context** out
   return LSBA_OK;
 }
 
+static void operator_release(lsba_operator* op);
+
 void lsba_context_destroy(lsba_context* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (lsba_operator* op : c->ops) {
+    operator_release(op);
+    op->ctx = nullptr;   // detached: lsba_operator_destroy then frees only the handle
+  }
+  c->ops.clear();
   ctx_release(c);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->ctl_host) (void)hipHostFree(c->ctl_host);
@@ -1248,12 +1285,13 @@ lsba_status lsba_operator_create_csr(lsba_context* c, int64_t n, int64_t nnz,
     lsba_operator_destroy(op);
     return fail(c, LSBA_ERR_HIP, e.msg);
   }
+  c->ops.insert(op);
   *out = op;
   return LSBA_OK;
 }
 
-void lsba_operator_destroy(lsba_operator* op) {
-  if (!op) return;
+// Release an operator's device memory (its context's stream drained first).
+static void operator_release(lsba_operator* op) {
   if (op->ctx) {
     (void)hipSetDevice(op->ctx->device);
     if (op->ctx->stream) (void)hipStreamSynchronize(op->ctx->stream);
@@ -1262,6 +1300,16 @@ void lsba_operator_destroy(lsba_operator* op) {
   if (op->ci) (void)hipFree(op->ci);
   if (op->val) (void)hipFree(op->val);
   if (op->val32) (void)hipFree(op->val32);
+  op->rp = nullptr;
+  op->ci = nullptr;
+  op->val = nullptr;
+  op->val32 = nullptr;
+}
+
+void lsba_operator_destroy(lsba_operator* op) {
+  if (!op) return;
+  operator_release(op);
+  if (op->ctx) op->ctx->ops.erase(op);
   delete op;
 }
 
@@ -1394,6 +1442,12 @@ lsba_status lsba_context_kernel_stats(const lsba_context* c, int32_t kind, int64
   if (launches) *launches = a.launches;
   if (total_ms) *total_ms = a.ms;
   if (total_bytes) *total_bytes = a.bytes;
+  return LSBA_OK;
+}
+
+lsba_status lsba_context_kernel_flops(const lsba_context* c, int32_t kind, double* total_flops) {
+  if (!c || kind < 0 || kind >= KK_COUNT || !total_flops) return LSBA_ERR_ARG;
+  *total_flops = c->timer ? c->timer->acc[kind].flops : 0.0;
   return LSBA_OK;
 }
 

@@ -35,6 +35,7 @@ EXPORTS = [
     "lsba_result_destroy", "lsba_context_set_timing", "lsba_context_kernel_stats",
     "lsba_solve_footprint", "lsba_server_create", "lsba_server_submit", "lsba_server_poll",
     "lsba_server_fetch", "lsba_server_stats", "lsba_server_destroy", "lsba_context_set_graphs",
+    "lsba_context_kernel_flops",
 ]
 
 KERNEL_KINDS = {"spmm": 0, "gram": 1, "gram_reduce": 2, "update": 3, "small": 4, "residual": 5}
@@ -73,6 +74,24 @@ class Params(ctypes.Structure):
 _lib = None
 
 
+def _init_torch_runtime_first():
+    """PyTorch wheels for ROCm ship their own HIP and HSA runtimes, so a
+    process that uses torch and this library holds two of each (device
+    pointers are shared: both map the process's one GPU address space).  If
+    the library's runtime opens the GPU first, torch's later initialisation
+    can find no device; initialising torch's first makes either order of use
+    work.  Nothing happens when torch is absent or sees no GPU."""
+    try:
+        import torch
+    except ImportError:
+        return
+    try:
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except Exception:
+        pass
+
+
 def load(path: str | None = None) -> ctypes.CDLL:
     """Load liblsba.so (built by ``paper_2208_09899_amd.build``)."""
     global _lib
@@ -81,6 +100,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise LibraryMissing(f"{p} not found: build it with `python -m paper_2208_09899_amd.build`")
+    _init_torch_runtime_first()
     lib = ctypes.CDLL(p)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
@@ -111,6 +131,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "lsba_context_set_graphs": (i32, [vp, ctypes.c_int]),
         "lsba_context_kernel_stats": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                             ctypes.POINTER(dbl)]),
+        "lsba_context_kernel_flops": (i32, [vp, i32, ctypes.POINTER(dbl)]),
         "lsba_solve_footprint": (ctypes.c_uint64, [i64, i32, vp]),
         "lsba_server_create": (i32, [vp, ctypes.c_uint64, i32, ctypes.POINTER(vp)]),
         "lsba_server_submit": (i32, [vp, vp, vp, i32, vp, i64, ctypes.c_int,
@@ -186,6 +207,15 @@ class Context:
             self.lib.lsba_context_kernel_stats(self.h, kind, ctypes.byref(n), ctypes.byref(ms),
                                                ctypes.byref(by))
             out[name] = (n.value, ms.value, by.value)
+        return out
+
+    def kernel_flops(self) -> dict:
+        """{kind: total algorithmic flops} of the timed launches since timing was enabled."""
+        out = {}
+        for name, kind in KERNEL_KINDS.items():
+            f = ctypes.c_double()
+            self.lib.lsba_context_kernel_flops(self.h, kind, ctypes.byref(f))
+            out[name] = f.value
         return out
 
     def close(self):

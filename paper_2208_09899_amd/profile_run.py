@@ -27,7 +27,7 @@ if __package__ in (None, ""):
 
 
 # kernel class: (kernel-name substrings, source file)
-KERNEL_CLASSES = {"update": (("update_kernel", "update_mfma8"), "kernels_update.hip"),
+KERNEL_CLASSES = {"update": (("update_kernel", "update_mfma"), "kernels_update.hip"),
                   "gram": (("gram_stage1", "gram_mfma"), "kernels_gram.hip"),
                   "spmm": (("spmm_kernel",), "kernels_sparse.hip")}
 
