@@ -22,7 +22,12 @@ Readings (where the paper is silent or ambiguous):
     grows).  With j = 0 the solve stops with status "breakdown".
   * A singular H_j (possible for nonsymmetric A) gives an infinite BFOM
     estimate for that column; BGMRES then falls back to the least-squares
-    form of its iterate (identical in exact arithmetic).
+    form of its iterate (identical in exact arithmetic).  If the last column
+    of a BFOM cycle has a singular H_j (no BFOM iterate exists), the cycle
+    ends with the least-squares iterate of that column instead.  After a
+    least-squares iterate the next cycle restarts from its residual block
+    V_{j+1} (E_1 B C - H_{j+1,j} Xi) with C = I (the factor M of Thm. 1 needs
+    H_j^{-T}).
   * ``max_cycles`` bounds the number of cycles; exhausting it returns the
     last iterate with status "not_converged".
 """
@@ -129,6 +134,8 @@ def solve(A, B, method: str = "gmres", skeleton: str = "bcgsi_ls", muscle: str =
                 loo_hist.append(float(np.linalg.norm(np.eye((j + 1) * s) - Vc.T @ Vc, 2)))
             if x_star is None:
                 crit = est / nB
+            elif Xi is None:
+                crit = np.inf
             else:
                 crit = np.linalg.norm(X + sk.Vcat(j) @ Xi - x_star) / np.linalg.norm(x_star)
             if crit <= tol:
@@ -145,6 +152,12 @@ def solve(A, B, method: str = "gmres", skeleton: str = "bcgsi_ls", muscle: str =
                                     cycle_len, m_after, ct.as_tuple(), cycles)
             m = j
             # Xi / M of column j are the last ones computed (columns are final in order)
+        if Xi is None:
+            # BFOM with a singular H_j at the cycle's last column: least-squares iterate
+            g = np.zeros(((j + 1) * s, s))
+            g[:s] = sk.Beta @ C
+            Xi = np.linalg.lstsq(sk.Hm1m(j), g, rcond=None)[0]
+            M = None
         Vj = sk.Vcat(j)
         X = X + Vj @ Xi
         cycle_len.append(j)

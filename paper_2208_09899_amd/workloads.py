@@ -23,6 +23,7 @@ paper Sec. 2, eq. AX=B):
   diagonal shift, rows ordered cell by cell for locality.
 * ``convdiff_2d(N, peclet, theta)``: centred-difference -Lap(u) + w.grad(u) on
   the unit square, |w| = peclet, scaled by h^2.
+* ``cyclic_shift(n)``: the permutation P e_i = e_{(i+1) mod n}.
 """
 from __future__ import annotations
 
@@ -159,6 +160,13 @@ def rgg_laplacian(n: int, seed: int = 3, degree: float = 4.0, shift: float = 1e-
     vals = np.concatenate([-w, -w, deg + shift])
     A = sp.coo_matrix((vals, (rows, cols)), shape=(n, n))
     return _from_scipy(A, f"rgg_n{n}_deg{degree:g}_shift{shift:g}")
+
+
+def cyclic_shift(n: int) -> CSR:
+    """The cyclic shift P e_i = e_{(i + 1) mod n} (a permutation matrix)."""
+    rows = (np.arange(n) + 1) % n
+    M = sp.csr_matrix((np.ones(n), (rows, np.arange(n))), shape=(n, n))
+    return _from_scipy(M, f"cyclic_shift_n{n}")
 
 
 def rhs(n: int, s: int, seed: int) -> np.ndarray:
