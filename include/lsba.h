@@ -189,6 +189,26 @@ lsba_status lsba_solve(lsba_context* ctx, const lsba_operator* op, const lsba_pa
                        int32_t s, const double* B, int64_t ldb, double* X, int64_t ldx,
                        int on_device, lsba_result** res);
 
+/* Variant of lsba_solve for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc): it calls no
+ * hipMalloc, hipFree or other device / pinned-memory allocator.  Its
+ * workspace (copies of B and X, the basis of m + 1 blocks, U, W, Gram
+ * partials, the small dense state, norm partials) is carved from a 64 MiB
+ * device array of the library, one per device, reserved when the library's
+ * code is loaded on that device and held until the process ends; a problem
+ * whose workspace exceeds it gives LSBA_ERR_ARG (nothing is written).  B and
+ * X are device pointers (n x s, row-major, leading dimensions ldb, ldx >= s).
+ * FP64 form only (LSBA_MIXED: LSBA_ERR_UNSUPPORTED).  Results are exactly
+ * those of lsba_solve with the same arguments; the result handle is host
+ * memory as there.  Kernel timing and cycle replay are suspended during the
+ * call.  All calls on one device share that device's array: calls that
+ * overlap in time on one device (several contexts or host threads) race and
+ * must be serialised by the caller.  Every value the solve reads from the
+ * array is written by the same call first.  Blocks until the solve ends. */
+lsba_status lsba_solve_noalloc(lsba_context* ctx, const lsba_operator* op, const lsba_params* prm,
+                               int32_t s, const double* B, int64_t ldb, double* X, int64_t ldx,
+                               lsba_result** res);
+
 /* Result getters.  Arrays are library-owned host memory, valid until
  * lsba_result_destroy.  res_hist[i] is the residual estimate (eq. normF_Rm)
  * over ||B||_F after the i-th final block column, over all cycles (for the

@@ -23,6 +23,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <set>
 #include <string>
 #include <type_traits>
@@ -35,6 +36,15 @@ using namespace lsba;
 namespace {
 struct EventTimer;
 }
+
+// Scratch memory of the no-allocation entry point (lsba_solve_noalloc): a
+// file-scope device array, one copy per device, held until the process
+// ends.  Host code never uses the array's name as an address: its device
+// address is taken once per device by hipGetSymbolAddress (scratch_init, at
+// context creation with that device current) and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 struct lsba_context {
   int device = 0;
@@ -239,6 +249,9 @@ struct Unsupported {
 };
 
 constexpr size_t kMaxGraphs = 8;
+// Stream-ordering events one cycle records: at most two per batch of side
+// jobs (about m / 4 + 5 batches) and two to join the side streams.
+constexpr int kMaxEvents = kMaxM / 2 + 16;
 
 // Destroy every captured cycle of a context (their launches may still be in
 // flight on the context's stream, so it is drained first).
@@ -980,6 +993,52 @@ lsba_status fail(lsba_context* c, lsba_status st, const std::string& msg) {
   return st;
 }
 
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of this device's copy of `scratch` (the current device is
+// `device`); taken once per device.
+void scratch_init(int device) {
+  if (device < 0 || device >= kScratchDevices) return;   // such devices get no scratch
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  g_scratch_ptr[device] = p;
+}
+
+// Bump allocation of 256-byte aligned pieces of one region (or, with
+// base == nullptr, just the bytes such pieces need).
+struct Bump {
+  char* base;
+  size_t used = 0;
+  void* take(size_t bytes) {
+    void* p = base ? base + used : reinterpret_cast<void*>(uintptr_t(4096));
+    used += align256(bytes);
+    return p;
+  }
+};
+
+// Device layout of one FP64 solve carved from a Bump region: B and X
+// copies, norm workspaces and the Krylov state.
+struct NoallocLayout {
+  double* B64 = nullptr;
+  double* X64 = nullptr;
+  NormWork nw;
+  Krylov<double> k{};
+};
+NoallocLayout noalloc_layout(Bump& b, int64_t n, int s, const lsba_params& p) {
+  NoallocLayout L;
+  const size_t blk64 = (size_t)n * s * sizeof(double);
+  L.B64 = (double*)b.take(blk64);
+  L.X64 = (double*)b.take(blk64);
+  L.nw.norm_partial = (double*)b.take(sizeof(double) * norm_partial_doubles((int64_t)n * s));
+  L.nw.res_partial = (double*)b.take(sizeof(double) * res_partial_doubles(n, s));
+  L.nw.out = (double*)b.take(sizeof(double) * 4);
+  L.k = make_krylov_with<double>([&b](const std::string&, size_t bytes) { return b.take(bytes); },
+                                 n, s, p.m, p, "n_");
+  return L;
+}
 
 }  // namespace
 
@@ -1183,7 +1242,17 @@ lsba_status lsba_context_create(int device, void* hip_stream, lsba_context** out
                          hipHostMallocDefault));
     HIPCHK(hipEventCreate(&c->ev0));
     HIPCHK(hipEventCreate(&c->ev1));
-    HIPCHK(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));  } catch (const HipError& e) {
+    HIPCHK(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
+    // the stream-ordering events a cycle records (two per batch of side jobs
+    // and two at its end: at most kMaxEvents for m <= kMaxM), created here so
+    // that solving creates none
+    for (int i = 0; i < kMaxEvents; ++i) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      c->evs.push_back(e);
+    }
+    scratch_init(device);
+  } catch (const HipError& e) {
     lsba_context_destroy(c);
     return fail(nullptr, LSBA_ERR_HIP, e.msg);
   }
@@ -1410,6 +1479,88 @@ lsba_status lsba_solve(lsba_context* c, const lsba_operator* op, const lsba_para
     delete r;
     return fail(c, LSBA_ERR_HIP, e.msg);
   }
+  *out = r;
+  return r->status;
+}
+
+lsba_status lsba_solve_noalloc(lsba_context* c, const lsba_operator* op,
+                               const lsba_params* prm, int32_t s, const double* B, int64_t ldb,
+                               double* X, int64_t ldx, lsba_result** out) {
+  if (!c) return fail(nullptr, LSBA_ERR_ARG, "context is NULL");
+  if (!op || !B || !X || !out) return fail(c, LSBA_ERR_ARG, "NULL pointer argument");
+  if (op->ctx != c) return fail(c, LSBA_ERR_ARG, "operator belongs to another context");
+  *out = nullptr;
+  try {
+    validate_params(prm, s);
+    if (ldb < s || ldx < s) throw ArgError{"ldb and ldx must be >= s"};
+    if (prm->precision != LSBA_FP64)
+      throw Unsupported{"lsba_solve_noalloc runs the FP64 form only"};
+  } catch (const ArgError& e) {
+    return fail(c, LSBA_ERR_ARG, e.msg);
+  } catch (const Unsupported& e) {
+    return fail(c, LSBA_ERR_UNSUPPORTED, e.msg);
+  }
+  const lsba_params p = *prm;
+  const int64_t n = op->n;
+  if (c->device < 0 || c->device >= kScratchDevices || !g_scratch_ptr[c->device])
+    return fail(c, LSBA_ERR_UNSUPPORTED, "no scratch memory on this device");
+  {
+    Bump need{nullptr};
+    (void)noalloc_layout(need, n, s, p);
+    if (need.used > kScratchBytes)
+      return fail(c, LSBA_ERR_ARG,
+                  "problem needs " + std::to_string(need.used) +
+                      " bytes of workspace; lsba_solve_noalloc has " +
+                      std::to_string(kScratchBytes));
+  }
+  auto* r = new (std::nothrow) lsba_result();
+  if (!r) return fail(c, LSBA_ERR_OOM, "host allocation failed");
+  // kernel timing (it creates events) and cycle capture (it instantiates
+  // graphs) are suspended for this call
+  EventTimer* saved_timer = c->timer;
+  const bool saved_graphs = c->graphs_on;
+  c->timer = nullptr;
+  c->graphs_on = false;
+  lsba_status ret = LSBA_OK;
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    Bump b{static_cast<char*>(g_scratch_ptr[c->device])};
+    NoallocLayout L = noalloc_layout(b, n, s, p);
+    HIPCHK(hipEventRecord(c->ev0, st));
+    HIPCHK(hipMemcpy2DAsync(L.B64, s * sizeof(double), B, ldb * sizeof(double),
+                            s * sizeof(double), n, hipMemcpyDeviceToDevice, st));
+    const double nB = device_norm(c, L.B64, n * s, &L.nw);
+    r->have_loo = (p.record & LSBA_REC_LOO) != 0;
+    if (nB == 0.0) {
+      HIPCHK(hipMemsetAsync(L.X64, 0, (size_t)n * s * sizeof(double), st));
+      r->status = LSBA_OK;
+      r->true_relres = 0.0;
+    } else {
+      CycleOut o = run_cycles<double>(c, op, p, L.k, op->val, L.B64, L.X64, nB, p.tol, r);
+      r->status = o.status;
+      r->iters = o.iters;
+      r->a = o.a;
+      r->v = o.v;
+      r->sy = o.sy;
+      if (p.record & LSBA_REC_TRUE_RES)
+        r->true_relres = device_residual(c, op, s, L.X64, L.B64, nullptr, &L.nw) / nB;
+    }
+    HIPCHK(hipMemcpy2DAsync(X, ldx * sizeof(double), L.X64, s * sizeof(double),
+                            s * sizeof(double), n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipEventRecord(c->ev1, st));
+    HIPCHK(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    r->gpu_ms = ms;
+  } catch (const HipError& e) {
+    delete r;
+    r = nullptr;
+    ret = fail(c, LSBA_ERR_HIP, e.msg);
+  }
+  c->timer = saved_timer;
+  c->graphs_on = saved_graphs;
+  if (!r) return ret;
   *out = r;
   return r->status;
 }

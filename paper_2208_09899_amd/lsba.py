@@ -35,7 +35,7 @@ EXPORTS = [
     "lsba_result_destroy", "lsba_context_set_timing", "lsba_context_kernel_stats",
     "lsba_solve_footprint", "lsba_server_create", "lsba_server_submit", "lsba_server_poll",
     "lsba_server_fetch", "lsba_server_stats", "lsba_server_destroy", "lsba_context_set_graphs",
-    "lsba_context_kernel_flops",
+    "lsba_solve_noalloc", "lsba_context_kernel_flops",
 ]
 
 KERNEL_KINDS = {"spmm": 0, "gram": 1, "gram_reduce": 2, "update": 3, "small": 4, "residual": 5}
@@ -114,6 +114,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "lsba_operator_destroy": (None, [vp]),
         "lsba_solve": (i32, [vp, vp, ctypes.POINTER(Params), i32, vp, i64, vp, i64,
                              ctypes.c_int, ctypes.POINTER(vp)]),
+        "lsba_solve_noalloc": (i32, [vp, vp, ctypes.POINTER(Params), i32, vp, i64, vp, i64,
+                                     ctypes.POINTER(vp)]),
         "lsba_result_status": (i32, [vp]),
         "lsba_result_iters": (i64, [vp]),
         "lsba_result_res_hist": (ctypes.POINTER(dbl), [vp]),
@@ -332,6 +334,25 @@ def solve(ctx: Context, op: Operator, B, X=None, **kw) -> Result:
     h = ctypes.c_void_p()
     st = lib.lsba_solve(ctx.h, op.h, ctypes.byref(p), s, bptr, ldb, xptr, ldx,
                         1 if on_dev else 0, ctypes.byref(h))
+    if st < 0:
+        raise LsbaError(st, ctx.error())
+    return _take_result(lib, h, X)
+
+
+def solve_noalloc(ctx: Context, op: Operator, B, X=None, **kw) -> Result:
+    """lsba_solve_noalloc: solve A X = B with the library's fixed device
+    workspace (B: n x s float64 torch CUDA tensor, row-major rows)."""
+    import torch
+    lib = ctx.lib
+    p = make_params(**kw)
+    assert _is_torch(B) and B.dtype == torch.float64 and B.dim() == 2 and B.stride(1) == 1
+    n, s = B.shape
+    if X is None:
+        X = torch.empty_like(B)
+    h = ctypes.c_void_p()
+    st = lib.lsba_solve_noalloc(ctx.h, op.h, ctypes.byref(p), s, ctypes.c_void_p(B.data_ptr()),
+                                B.stride(0), ctypes.c_void_p(X.data_ptr()), X.stride(0),
+                                ctypes.byref(h))
     if st < 0:
         raise LsbaError(st, ctx.error())
     return _take_result(lib, h, X)
