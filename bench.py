@@ -1,14 +1,19 @@
 """Benchmark: restarted block Krylov solves on one MI355X through the C ABI.
 
-Default workload: 2-D 5-point Dirichlet Laplacian on a 256 x 256 grid
-(n = 65536), s = 8 seeded N(0,1) right-hand sides, m = 30, tol 1e-8 on the
-relative residual estimate; one step = the six FP64 solves BFOM and BGMRES x
-{BCGSI+LS, BMGS-CWY, BMGS-ICWY} with CholQR.  value = solves per second.
+Default workload: 3-D 7-point Laplacian on a 128^3 grid (n = 2,097,152,
+nnz 14,581,760), s = 32 seeded N(0,1) right-hand sides, BGMRES with the
+BCGSI+LS skeleton and CholQR, m = 20, tol 1e-10 on the relative residual
+estimate, FP64; one step = one complete solve.  value = solves per second.
+The precision form (FP32 inner solves, FP64 refinement) is timed beside it on
+the same problem.  The 2-D Laplacian workload (256^2, s = 8, m = 30, six
+solves per step) is ``--workload laplace2d``; its 130 MB basis is resident
+in the 256 MB Infinity Cache, so its GB/s are not HBM figures.
 
 Prints one JSON line with the throughput, the block-Arnoldi GB/s, a roofline
-record for the dominant kernel class (algorithmic bytes over its HIP-event
-device time, measured live over the timed region) and the CPU oracle timed
-on a bounded sample of the same workload.
+record for the dominant kernel class (algorithmic bytes and flops over its
+HIP-event device time, measured live over the timed region, against
+max(bytes / 8 TB/s, flops / 78.6 TFLOP/s FP64)) and the CPU oracle timed on a
+bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 """
@@ -28,6 +33,7 @@ if ROOT not in sys.path:
 
 METRIC = "block-Arnoldi GB/s + solves/s at rel. residual 1e-8; serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6       # MI355X dense FP64 matrix / vector peak (published)
 
 WORKLOADS = {
     # name: (workload key, scale, solve list [(method, skeleton)], precision, s, note)
@@ -82,11 +88,12 @@ def cpu_baseline(wl, solves, gpu_iters, budget_s=15.0):
     method, skel = solves[0]
     A = wl.A.to_scipy()
     # calibrate: a few iterations, then a sample sized to the budget
+    ncal = 2 if wl.A.n > 10 ** 6 else 5
     t0 = time.perf_counter()
     oracle.solve(A, wl.B, method, skel, "cholqr", m=wl.m, tol=0.0, max_cycles=10 ** 6,
-                 max_iters=5)
-    t_cal = (time.perf_counter() - t0) / 5
-    k = int(max(10, min(2000, budget_s / max(t_cal, 1e-6))))
+                 max_iters=ncal)
+    t_cal = (time.perf_counter() - t0) / ncal
+    k = int(max(4, min(2000, budget_s / max(t_cal, 1e-6))))
     t0 = time.perf_counter()
     r = oracle.solve(A, wl.B, method, skel, "cholqr", m=wl.m, tol=0.0, max_cycles=10 ** 6,
                      max_iters=k)
@@ -184,9 +191,11 @@ def run_serving(args, torch, lsba, w):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="laplace2d", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--workload", default="laplace3d", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="do not time the precision form beside the FP64 solve")
     ap.add_argument("--requests", type=int, default=512, help="serving: stream length")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
@@ -230,13 +239,20 @@ def main():
     torch.cuda.synchronize()
     stats, dom = {}, None
     if not args.no_timing:
-        # one untimed step with every kernel class bracketed by HIP events: the
+        # an untimed run with every kernel class bracketed by HIP events: the
         # per-class breakdown, and which class dominates the device time
+        # (for large problems two restart cycles of the first solve suffice)
         ctx.set_timing(True)
-        log("[bench] profiling step (all kernel classes timed, not in the timed region)")
-        step()
+        log("[bench] profiling run (all kernel classes timed, not in the timed region)")
+        if n * s > 10 ** 7:
+            method, skel = solves[0]
+            lsba.solve(ctx, op, B, X=X, method=method, skeleton=skel,
+                       **dict(kw, max_iters=2 * wl.m + 2))
+        else:
+            step()
         torch.cuda.synchronize()
         stats = ctx.kernel_stats()
+        flops_prof = ctx.kernel_flops()
         dom = max(("spmm", "gram", "update"), key=lambda k: stats[k][1])
         # the timed steps bracket only the dominant class, which perturbs them least
         ctx.set_timing(True, kinds=[dom])
@@ -250,6 +266,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     live = ctx.kernel_stats() if dom else {}
+    live_flops = ctx.kernel_flops() if dom else {}
     ctx.set_timing(False)
     elapsed = t1 - t0
     nsolves = len(solves) * args.steps
@@ -284,18 +301,36 @@ def main():
         line["arnoldi_gbps"] = tot_b / (tot_ms * 1e-3) / 1e9 if tot_ms else None
         line["kernel_stats"] = {k: {"launches": v[0], "ms": round(v[1], 3),
                                     "alg_GB": round(v[2] / 1e9, 4)} for k, v in stats.items()}
+        line["kernel_stats_note"] = ("profiling run: " + ("first two restart cycles of the "
+                                     "first solve" if n * s > 10 ** 7 else "one whole step"))
+        for k in ("spmm", "gram", "update"):
+            line["kernel_stats"][k]["alg_GFLOP"] = round(flops_prof[k] / 1e9, 3)
         launches, ms, by = live[dom]
-        achieved = by / (ms * 1e-3) / 1e9 if ms else 0.0
+        fl = live_flops[dom]
+        # roofline of the dominant class: the time its launches need at the
+        # HBM peak or at the FP64 peak, whichever is longer, over the time
+        # they took (per-launch bytes and flops grow together, so the sums
+        # decide the bound as the single launches do)
+        t_b = by / (HBM_PEAK_GBS * 1e9)
+        t_f = fl / (FP64_PEAK_TFS * 1e12)
+        sec = ms * 1e-3
+        if t_f > t_b:
+            bound, achieved, peak, unit = "mfma", fl / sec / 1e12, FP64_PEAK_TFS, "TFLOP/s"
+        else:
+            bound, achieved, peak, unit = "hbm", by / sec / 1e9, HBM_PEAK_GBS, "GB/s"
         line["roofline"] = {
             "kernel": dom,
-            "bound": "hbm",
+            "bound": bound,
             "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "peak": peak,
+            "unit": unit,
+            "frac": achieved / peak,
             "traffic": None,
+            "hbm_gbs": by / sec / 1e9 if sec else None,
+            "fp64_tflops": fl / sec / 1e12 if sec else None,
             "avg_launch_us": 1e3 * ms / launches if launches else None,
             "alg_bytes_per_launch": by / launches if launches else None,
+            "alg_flops_per_launch": fl / launches if launches else None,
             "launches": launches,
         }
     if "roofline" in line:
@@ -305,6 +340,27 @@ def main():
             line["roofline"]["traffic_note"] = (
                 f"calibrated FETCH_SIZE+WRITE_SIZE per launch over {tr['launches']} launches "
                 f"(algorithmic bytes per launch in that run {tr['alg_bytes_per_launch']:.4g})")
+    if precision == "fp64" and not args.no_mixed and len(solves) == 1:
+        # the precision form on the same problem, beside the headline (not in
+        # the timed region): time to the same tolerance, true residual, and
+        # its difference from the FP64 solution just computed
+        method, skel = solves[0]
+        Xm = torch.empty_like(B)
+        log("[bench] precision form (FP32 inner solves, FP64 refinement) ...")
+        torch.cuda.synchronize()
+        tm0 = time.perf_counter()
+        rm = lsba.solve(ctx, op, B, X=Xm, method=method, skeleton=skel,
+                        **dict(kw, precision="mixed"))
+        torch.cuda.synchronize()
+        tm1 = time.perf_counter()
+        fp64_ms = 1e3 * elapsed / args.steps / len(solves)
+        line["mixed"] = {
+            "status": rm.status, "ms": round(1e3 * (tm1 - tm0), 1),
+            "inner_iters": rm.iters, "refine_steps": rm.refine_steps,
+            "true_relres": rm.true_relres,
+            "err_vs_fp64": float(torch.linalg.norm(Xm - X) / torch.linalg.norm(X)),
+            "speedup_vs_fp64": fp64_ms / (1e3 * (tm1 - tm0)),
+        }
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample ...")
         line["cpu_baseline"] = cpu_baseline(wl, solves, [r["iters"] for r in res])
