@@ -256,8 +256,8 @@ constexpr int kWTR = 16;              // rows per right-operand stage
 constexpr int kWQB = 64;              // largest right width (two blocks of 32)
 constexpr int kWLD = kWQB + 16;       // LDS row stride of a stage (doubles)
 
-template <int SW, int NTR, int RPT>
-__global__ __launch_bounds__(512) void gram_mfma_wide(GramArgs<double> a, int nchunk, int ngroup,
+template <typename T, int SW, int NTR, int RPT>
+__global__ __launch_bounds__(512) void gram_mfma_wide(GramArgs<T> a, int nchunk, int ngroup,
                                                       int wpg, int64_t rows_per_chunk,
                                                       double* __restrict__ partial,
                                                       const Ctl* __restrict__ ctl) {
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(512) void gram_mfma_wide(GramArgs<double> a, int nc
   const int lr = lane & 15, lk = lane >> 4;
   // strip base pointers are the same for every lane (a strip never
   // straddles two blocks); the lane's column adds lr
-  const double* Lp[SW];
+  const T* Lp[SW];
 #pragma unroll
   for (int i = 0; i < SW; ++i) {
     const int col = (st0 + (i < nsw ? i : (nsw > 0 ? nsw - 1 : 0))) * 16;
@@ -291,22 +291,24 @@ __global__ __launch_bounds__(512) void gram_mfma_wide(GramArgs<double> a, int nc
   const int64_t r1 = r0 + rows_per_chunk < a.n ? r0 + rows_per_chunk : a.n;
   const int nst = (int)((r1 - r0 + kWTR - 1) / kWTR);
   // right-stage staging: 16-byte chunk e = threadIdx.x + blockDim.x u of the
-  // stage is (row e / cpr, chunk e % cpr); RPT >= chunks per thread
-  const int cpr = QB >> 1;                      // chunks per right row
+  // stage is (row e / cpr, chunk e % cpr); RPT >= chunks per thread.  FP32
+  // blocks are widened to FP64 when written to LDS.
+  constexpr int EPC = 16 / (int)sizeof(T);      // elements per 16-byte chunk
+  const int cpr = QB / EPC;                     // chunks per right row
   const int nchk = kWTR * cpr;
-  typedef double wd2 __attribute__((ext_vector_type(2)));
-  wd2 rreg[RPT];
+  typedef T wv __attribute__((ext_vector_type(EPC)));
+  wv rreg[RPT];
   auto rload = [&](int st) {
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       const int e = threadIdx.x + blockDim.x * u;
       if (e < nchk) {
-        const int row = e / cpr, col = 2 * (e % cpr);
+        const int row = e / cpr, col = EPC * (e % cpr);
         const int64_t grow = r0 + (int64_t)st * kWTR + row;
         const bool ok = grow < r1;
-        const wd2 v = *reinterpret_cast<const wd2*>(a.xr[col / s] + (col % s) +
-                                                    (ok ? grow : r1 - 1) * s);
-        rreg[u] = ok ? v : wd2{0.0, 0.0};   // rows past r1 contribute 0
+        const wv v = *reinterpret_cast<const wv*>(a.xr[col / s] + (col % s) +
+                                                  (ok ? grow : r1 - 1) * s);
+        rreg[u] = ok ? v : wv(T(0));   // rows past r1 contribute 0
       }
     }
   };
@@ -314,8 +316,11 @@ __global__ __launch_bounds__(512) void gram_mfma_wide(GramArgs<double> a, int nc
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       const int e = threadIdx.x + blockDim.x * u;
-      if (e < nchk)
-        *reinterpret_cast<wd2*>(&rs[buf][(e / cpr) * kWLD + 2 * (e % cpr)]) = rreg[u];
+      if (e < nchk) {
+        double* dst = &rs[buf][(e / cpr) * kWLD + EPC * (e % cpr)];
+#pragma unroll
+        for (int q = 0; q < EPC; ++q) dst[q] = (double)rreg[u][q];
+      }
     }
   };
   // left fragments of the four row groups of a stage (slot kq)
@@ -325,7 +330,7 @@ __global__ __launch_bounds__(512) void gram_mfma_wide(GramArgs<double> a, int nc
     const int64_t off = (row < r1 ? row : r1 - 1) * s;
 #pragma unroll
     for (int i = 0; i < SW; ++i)
-      if (i < nsw) av[kq][i] = Lp[i][off];
+      if (i < nsw) av[kq][i] = (double)Lp[i][off];
   };
   gd4 acc[SW][NTR];
 #pragma unroll
@@ -510,14 +515,14 @@ void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* 
                  const Ctl* ctl, KTimer* tm) {
   const int PA = (a.nv + a.nxl) * a.s, QB = a.nxr * a.s;
   const double gflops = 2.0 * (double)a.n * PA * QB;
-  if constexpr (sizeof(T) == sizeof(double)) {
-    if (use_wide(a.s, QB)) {
+  if (use_wide(a.s, QB)) {
+    {
       const WPlan q = wplan(a.n, PA, QB);
       const int nchunk_pad = ((q.nchunk + kXcds - 1) / kXcds) * kXcds;
       const dim3 g(nchunk_pad * q.ngroup), b(64 * q.wpg);
       const double bytes = (double)distinct_blocks(a) * a.n * a.s * sizeof(T);
 #define LSBA_WIDE(SW, NTR)                                                                   \
-  launch_kf(tm, KK_GRAM, bytes, gflops, gram_mfma_wide<SW, NTR, (SW > 4 ? 1 : 8)>, g, b, 0,          \
+  launch_kf(tm, KK_GRAM, bytes, gflops, gram_mfma_wide<T, SW, NTR, (SW > 4 ? 1 : 8)>, g, b, 0,       \
            st, a, q.nchunk, q.ngroup, q.wpg, q.rows, partial, ctl)
       if (q.sw == 4) {
         if (q.ntr == 4) LSBA_WIDE(4, 4);
@@ -532,6 +537,8 @@ void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* 
       launch_stage2(st, partial, q.nchunk, PA * QB, out, ctl, tm);
       return;
     }
+  }
+  if constexpr (sizeof(T) == sizeof(double)) {
     if (use_mfma(a.s)) {
       const MPlan q = mplan(a.n, PA, QB);
       const int nchunk_pad = ((q.nchunk + kXcds - 1) / kXcds) * kXcds;

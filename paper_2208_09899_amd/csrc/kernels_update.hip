@@ -441,6 +441,224 @@ __global__ __launch_bounds__(512) void update_mfma_wide(UpdateArgs<double> a,
     }
 }
 
+// FP32 blocks, s = 16 or 32, on the BF16 matrix cores with FP32
+// accumulation: every FP32 operand x is split into bf16 parts
+// x = hi + lo (hi = x rounded to bfloat16, lo = the rounded remainder), and
+// each product takes hi*hi + hi*lo + lo*hi (the dropped lo*lo is below
+// 2^-16 relative), so the update keeps close to FP32 accuracy at the BF16
+// matrix rate.  Product shape as in update_mfma_wide: [out1 | out2] = the
+// input rows times the stacked coefficient rows, one K = s product per
+// input block and 16-column output tile (v_mfma_f32_16x16x32_bf16 for
+// s = 32, v_mfma_f32_16x16x16bf16_1k for s = 16): lane l holds row l % 16
+// and the KPL = s / 4 consecutive input columns KPL (l / 16) .. of it (one
+// or two 16-byte loads), the coefficient fragment holds the same rows of
+// the coefficient block, and the result rows 4 (l / 16) + r of column l % 16.
+// A workgroup of 8 wavefronts owns 256 rows; each input's coefficient
+// fragments, already split into bf16 hi / lo, are staged in LDS once per
+// workgroup, double-buffered; the next input's rows load while the current
+// one is multiplied.
+typedef short us8 __attribute__((ext_vector_type(8)));
+typedef short us4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bfv8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bfv4 __attribute__((ext_vector_type(4)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+
+// bfloat16 is the upper half of an FP32 word; round to nearest, ties to even.
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  const unsigned int u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_value(unsigned short b) {
+  return __uint_as_float((unsigned int)b << 16);
+}
+// x = hi + lo with hi, lo bfloat16 (bit patterns)
+__device__ __forceinline__ void bf16_split(float x, short& hi, short& lo) {
+  const unsigned short h = bf16_bits(x);
+  hi = (short)h;
+  lo = (short)bf16_bits(x - bf16_value(h));
+}
+
+template <int KPL>
+__device__ __forceinline__ fv4 mfma_bf16(const short (&a)[KPL], const short (&b)[KPL], fv4 c) {
+  if constexpr (KPL == 8) {
+    us8 av, bv;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      av[e] = a[e];
+      bv[e] = b[e];
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bfv8, av),
+                                                   __builtin_bit_cast(bfv8, bv), c, 0, 0, 0);
+  } else {
+    us4 av, bv;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      av[e] = a[e];
+      bv[e] = b[e];
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bfv4, av),
+                                                     __builtin_bit_cast(bfv4, bv), c, 0, 0, 0);
+  }
+}
+
+template <int S, bool FOLD>
+__global__ __launch_bounds__(512) void update_bf16x3(UpdateArgs<float> a,
+                                                     const Ctl* __restrict__ ctl, int obey_stop) {
+  constexpr int NT = 2 * S / 16;    // output tiles of 16 columns
+  constexpr int KPL = S / 4;        // input columns per lane
+  constexpr int RG = 2;             // row groups of 16 per wavefront
+  constexpr int FR = NT * 64 * KPL; // bf16 values of one part (hi or lo) of an input's fragments
+  __shared__ short cf[2][2][FR];    // [buffer][hi / lo][tile][lane][KPL]
+  if (obey_stop && ctl && ctl->stop) return;
+  int nv1 = a.nv1, nb = a.nv2_begin, nv2 = a.nv2;
+  if (a.nvp) {
+    nv1 = a.nvp[0];
+    nb = a.nvp[1];
+    nv2 = a.nvp[2];
+    if (nv1 < 0) return;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int64_t wrow0 = (int64_t)blockIdx.x * (8 * RG * 16) + (int64_t)wave * (RG * 16);
+  const int nvmax = nv1 > nv2 ? nv1 : nv2;
+  InputSeq<float> in;
+  in.in1 = a.in1;
+  in.in2 = a.in2;
+  in.V = a.V;
+  in.off = 0;
+  in.bstride = a.n * S;
+  in.h1 = a.in1 ? 1 : 0;
+  in.i0 = nv1 > 0 ? 0 : nb;
+  if (FOLD && nv1 > 0) in.i0 = 0;
+  in.nbas = nvmax > in.i0 ? nvmax - in.i0 : 0;
+  in.nv1 = nv1;
+  in.nb = nb;
+  in.nv2 = nv2;
+  const int nin = in.h1 + in.nbas + (a.in2 ? 1 : 0);
+  int64_t roff[RG];
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    const int64_t row = wrow0 + 16 * g + lr;
+    roff[g] = (row < a.n ? row : a.n - 1) * S + KPL * lq;
+  }
+  // coefficient entries this thread splits and stages: e = threadIdx.x + 512 u
+  // over [tile][lane][KPL]
+  constexpr int CPT = (FR + 511) / 512;
+  auto coef_load = [&](int q, float (&cv)[CPT]) {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int e = threadIdx.x + 512 * u;
+      float v = 0.f;
+      if (e < FR) {
+        const int t = e / (64 * KPL), rem = e % (64 * KPL);
+        const int l = rem / KPL, kk = rem % KPL;
+        const int half = t / (NT / 2);
+        const int col = (t % (NT / 2)) * 16 + (l & 15);
+        const int krow = KPL * (l >> 4) + kk;
+        const float* blk = nullptr;
+        if (q < in.h1) {
+          blk = half ? (FOLD ? a.coef + a.lay.C1D() : nullptr) : a.coef + a.lay.C1();
+        } else if (q - in.h1 < in.nbas) {
+          const int i = in.i0 + q - in.h1;
+          if (!half) blk = i < nv1 ? a.coef + a.lay.A(i) : nullptr;
+          else if (FOLD) blk = a.coef + a.lay.BF(i);
+          else blk = (i >= nb && i < nv2) ? a.coef + a.lay.B(i) : nullptr;
+        } else {
+          blk = half ? a.coef + a.lay.C2() : nullptr;
+        }
+        if (blk) v = blk[krow * S + col];
+      }
+      cv[u] = v;
+    }
+  };
+  auto coef_store = [&](int buf, const float (&cv)[CPT]) {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int e = threadIdx.x + 512 * u;
+      if (e < FR) {
+        short h, l;
+        bf16_split(cv[u], h, l);
+        cf[buf][0][e] = h;
+        cf[buf][1][e] = l;
+      }
+    }
+  };
+  typedef float flv4 __attribute__((ext_vector_type(4)));
+  constexpr int NLD = KPL / 4;   // 16-byte loads per lane and row group
+  auto rows_load = [&](int q, flv4 (&x)[RG][NLD]) {
+    const float* p = in.ptr(q);
+#pragma unroll
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+      for (int j = 0; j < NLD; ++j) x[g][j] = *reinterpret_cast<const flv4*>(p + roff[g] + 4 * j);
+  };
+  fv4 acc[RG][NT];
+#pragma unroll
+  for (int g = 0; g < RG; ++g)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[g][t] = fv4{0.f, 0.f, 0.f, 0.f};
+  flv4 xc[RG][NLD], xn[RG][NLD];
+  float cvn[CPT];
+  if (nin > 0) {
+    coef_load(0, cvn);
+    rows_load(0, xc);
+    coef_store(0, cvn);
+  }
+  __syncthreads();
+  for (int q = 0; q < nin; ++q) {
+    const int buf = q & 1;
+    const bool more = q + 1 < nin;
+    if (more) {
+      coef_load(q + 1, cvn);
+      rows_load(q + 1, xn);
+    }
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      short ah[KPL], al[KPL];
+#pragma unroll
+      for (int e = 0; e < KPL; ++e) bf16_split(xc[g][e >> 2][e & 3], ah[e], al[e]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        short bh[KPL], bl[KPL];
+#pragma unroll
+        for (int e = 0; e < KPL; ++e) {
+          bh[e] = cf[buf][0][(t * 64 + lane) * KPL + e];
+          bl[e] = cf[buf][1][(t * 64 + lane) * KPL + e];
+        }
+        acc[g][t] = mfma_bf16<KPL>(al, bh, acc[g][t]);
+        acc[g][t] = mfma_bf16<KPL>(ah, bl, acc[g][t]);
+        acc[g][t] = mfma_bf16<KPL>(ah, bh, acc[g][t]);
+      }
+    }
+    if (more) {
+      coef_store(buf ^ 1, cvn);
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int j = 0; j < NLD; ++j) xc[g][j] = xn[g][j];
+    }
+    __syncthreads();
+  }
+  const bool w2 = a.out2 && (a.in2 || nv2 > nb);
+#pragma unroll
+  for (int g = 0; g < RG; ++g)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = wrow0 + 16 * g + 4 * lq + r;
+      if (row >= a.n) continue;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int half = t / (NT / 2);
+        const int col = (t % (NT / 2)) * 16 + lr;
+        if (!half) {
+          if (a.out1) a.out1[row * S + col] = acc[g][t][r];
+        } else if (w2) {
+          a.out2[row * S + col] = acc[g][t][r];
+        }
+      }
+    }
+}
+
 template <typename T, int S>
 void launch_s(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey, KTimer* tm,
               double bytes, double flops) {
@@ -455,6 +673,18 @@ void launch_s(hipStream_t st, const UpdateArgs<T>& a, const Ctl* ctl, bool obey,
         launch_kf(tm, KK_UPDATE, bytes, flops, update_mfma8<true>, g, dim3(256), 0, st, a, ctl, ob);
       else
         launch_kf(tm, KK_UPDATE, bytes, flops, update_mfma8<false>, g, dim3(256), 0, st, a, ctl, ob);
+      return;
+    }
+  }
+  if constexpr (sizeof(T) == sizeof(float) && (S == 16 || S == 32)) {
+    if (a.s == S) {
+      const dim3 g((unsigned)((a.n + 255) / 256));
+      if (a.has_D)
+        launch_kf(tm, KK_UPDATE, bytes, flops, update_bf16x3<S, true>, g, dim3(512), 0, st, a, ctl,
+                  ob);
+      else
+        launch_kf(tm, KK_UPDATE, bytes, flops, update_bf16x3<S, false>, g, dim3(512), 0, st, a,
+                  ctl, ob);
       return;
     }
   }

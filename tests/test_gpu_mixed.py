@@ -72,3 +72,31 @@ def test_mixed_graph_laplacian_restarts():
           f"difference to FP64 solve {err:.2e}")
     assert g64.status == "ok"
     assert err <= 1e5 * (r + r64)
+
+
+def test_mixed_kappa_1e6_graph_laplacian():
+    """The precision form on an ill-conditioned operator of the random
+    geometric graph class: n = 2^14 points, mean degree 8 (above the 2-D
+    percolation threshold: 16 components, the largest 16355 nodes) + 1e-5 I.
+    lambda_min is exactly the shift (the constant vector of each component)
+    and lambda_max = 13.1, so kappa = 1.3e6.  BGMRES(25) with BCGSI+LS,
+    s = 16: FP32 inner solves with u_32 kappa ~ 0.08 each win only about
+    one digit, so refinement does the rest; the solve must reach a true
+    relative residual of 1e-8.  Its error against a direct FP64 solution is
+    formed by the library (lsba_result_err_vs_ref) and must satisfy the
+    residual bound kappa r (plus the direct solve's own rounding)."""
+    import scipy.sparse.linalg as sla
+    A = w.rgg_laplacian(1 << 14, seed=3, degree=8.0, shift=1e-5)
+    B = w.rhs(A.n, 16, seed=4)
+    As = A.to_scipy().tocsc()
+    X_ref = sla.spsolve(As, B)
+    tol = 1e-8
+    g = gpu_solve(A, B, method="gmres", skeleton="bcgsi_ls", m=25, tol=tol, max_cycles=3000,
+                  precision="mixed", max_refine=40, inner_tol=1e-4, x_ref=X_ref)
+    r = true_relres(A, g.X, B)
+    print(f"mixed kappa 1.3e6: status {g.status}, refinement steps {g.refine_steps}, inner block "
+          f"iterations {g.iters}, true relres {r:.2e}, error vs direct {g.err_vs_ref:.2e}")
+    assert g.status == "ok", (g.status, g.refine_steps, g.true_relres)
+    assert r <= tol
+    kappa = 13.13 / 1e-5
+    assert g.err_vs_ref <= kappa * (r + 1e-12)
