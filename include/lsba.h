@@ -227,6 +227,17 @@ const int32_t* lsba_result_m_after(const lsba_result* r);
 void lsba_result_counts(const lsba_result* r, int64_t* a_calls, int64_t* v_apps, int64_t* syncs);
 /* ||B - A X||_F / ||B||_F in FP64 (NaN unless LSBA_REC_TRUE_RES or LSBA_MIXED). */
 double lsba_result_true_relres(const lsba_result* r);
+/* Error of a solution against a reference solution, e.g. the FP64 CPU
+ * oracle's X on the same inputs: lsba_result_set_err_vs_ref forms
+ * ||X - Xref||_F / ||Xref||_F in FP64 on the context's device (fixed-order
+ * reductions; X and Xref n x s row-major with leading dimensions ldx, ldr,
+ * host or device memory per on_device; neither is modified) and stores it
+ * in r; lsba_result_err_vs_ref returns it, NaN until set.  The library does
+ * not compute the reference itself. */
+lsba_status lsba_result_set_err_vs_ref(lsba_context* ctx, lsba_result* r, int64_t n, int32_t s,
+                                       const double* X, int64_t ldx, const double* Xref,
+                                       int64_t ldr, int on_device);
+double lsba_result_err_vs_ref(const lsba_result* r);
 /* Outer refinement steps taken (LSBA_MIXED), else 0. */
 int32_t lsba_result_refine_steps(const lsba_result* r);
 /* Device time of the solve in milliseconds (HIP events around the whole solve). */
@@ -259,8 +270,9 @@ uint64_t lsba_solve_footprint(int64_t n, int32_t s, const lsba_params* params);
 lsba_status lsba_server_create(lsba_context* ctx, uint64_t hbm_budget_bytes, int32_t max_slots,
                                lsba_server** out);
 
-/* Queue a request (non-blocking).  B (n x s, row-major, ld ldb; host memory,
- * or device memory if on_device) is copied; *ticket identifies the request.
+/* Queue a request.  B (n x s, row-major, ld ldb; host memory, or device
+ * memory if on_device) is copied into pinned host memory (the call returns
+ * once the copy is done); *ticket identifies the request.
  * The parameters are validated as in lsba_solve; the serving form runs FP64
  * only (LSBA_MIXED: LSBA_ERR_UNSUPPORTED).  A footprint above the budget is
  * LSBA_ERR_OOM (it could never be admitted). */
@@ -268,8 +280,11 @@ lsba_status lsba_server_submit(lsba_server* srv, const lsba_operator* op,
                                const lsba_params* params, int32_t s, const double* B,
                                int64_t ldb, int on_device, uint64_t* ticket);
 
-/* Progress engine: end the cycles whose work has completed and queue the next
- * ones, finish requests, admit queued requests; never waits for the GPU.
+/* Progress engine: advance every slot whose queued work has completed (the
+ * upload of B and its norm, a restart cycle, or the end of a request: true
+ * residual and download of X into pinned memory) and queue the next step,
+ * then admit queued requests; it only queries events and never waits for
+ * the GPU.
  * Writes up to cap tickets of requests finished since the last report to
  * done[] and their number to *n_done (the rest are reported by later calls). */
 lsba_status lsba_server_poll(lsba_server* srv, uint64_t* done, int32_t cap, int32_t* n_done);

@@ -135,6 +135,29 @@ __global__ __launch_bounds__(256) void sumsq_partial_kernel(int64_t count,
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
+// Per-workgroup sums of (X - Y)^2 over an n x s block (row-major, leading
+// dimensions ldx, ldy); each workgroup takes per_block consecutive entries.
+__global__ __launch_bounds__(256) void diff_sumsq_partial_kernel(int64_t n, int s,
+                                                                 const double* __restrict__ X,
+                                                                 int64_t ldx,
+                                                                 const double* __restrict__ Y,
+                                                                 int64_t ldy,
+                                                                 double* __restrict__ partial,
+                                                                 int64_t per_block) {
+  __shared__ double sh[4];
+  const int64_t count = n * s;
+  const int64_t b0 = (int64_t)blockIdx.x * per_block;
+  const int64_t b1 = b0 + per_block < count ? b0 + per_block : count;
+  double sq = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) {
+    const int64_t r = i / s, c = i % s;
+    const double d = X[r * ldx + c] - Y[r * ldy + c];
+    sq += d * d;
+  }
+  const double tot = block_sum_256(sq, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
 __global__ __launch_bounds__(256) void sumsq_final_kernel(const double* __restrict__ partial,
                                                           int nw, double* __restrict__ out) {
   __shared__ double sh[4];
@@ -211,6 +234,16 @@ void launch_sumsq_partial(hipStream_t st, int64_t count, const double* x, double
   int64_t blocks = (count + per - 1) / per;
   if (blocks < 1) blocks = 1;
   sumsq_partial_kernel<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(count, x, partial, per);
+  *nw_out = (int)blocks;
+}
+
+void launch_diff_sumsq_partial(hipStream_t st, int64_t n, int s, const double* X, int64_t ldx,
+                               const double* Y, int64_t ldy, double* partial, int* nw_out) {
+  const int64_t per = 256 * 16;
+  int64_t blocks = (n * s + per - 1) / per;
+  if (blocks < 1) blocks = 1;
+  diff_sumsq_partial_kernel<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(n, s, X, ldx, Y, ldy,
+                                                                         partial, per);
   *nw_out = (int)blocks;
 }
 

@@ -166,6 +166,10 @@ void launch_residual(hipStream_t st, int64_t n, int64_t nnz, int s, const int64_
 void launch_sumsq_partial(hipStream_t st, int64_t count, const double* x, double* partial,
                           int* nw_out);
 void launch_sumsq_final(hipStream_t st, const double* partial, int nw, double* out_norm);
+// partial[w] = sum over workgroup w's entries of (X - Y)^2 (n x s, leading
+// dimensions ldx, ldy), nw_out = number of workgroups (n s / 4096 rounded up)
+void launch_diff_sumsq_partial(hipStream_t st, int64_t n, int s, const double* X, int64_t ldx,
+                               const double* Y, int64_t ldy, double* partial, int* nw_out);
 template <typename T>
 void launch_cast(hipStream_t st, int64_t count, const double* in, T* out);
 template <typename T>

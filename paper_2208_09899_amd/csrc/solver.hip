@@ -100,6 +100,7 @@ struct lsba_result {
   std::vector<int32_t> cyc, mafter;
   int64_t a = 0, v = 0, sy = 0;
   double true_relres = NAN;
+  double err_vs_ref = NAN;   // set by lsba_result_set_err_vs_ref
   int32_t refine = 0;
   double gpu_ms = 0.0;
   bool have_loo = false;
@@ -908,9 +909,14 @@ struct SrvRequest {
   int s = 0;
   int64_t n = 0;
   uint64_t footprint = 0;
-  std::vector<double> B, X;
+  double* Bh = nullptr;   // pinned host copy of B (n x s), until the request ends
+  double* Xh = nullptr;   // pinned host X (n x s), filled when the request ends
   lsba_result* res = nullptr;
   int state = 0;   // 0 queued, 1 running, 2 done
+  ~SrvRequest() {
+    if (Bh) (void)hipHostFree(Bh);
+    if (Xh) (void)hipHostFree(Xh);
+  }
 };
 
 // A slot runs one admitted request on its own context (streams, events,
@@ -923,7 +929,10 @@ struct SrvSlot {
   double* B64 = nullptr;
   double* X64 = nullptr;
   double nB = 0.0;
-  bool in_flight = false;
+  // work queued on the slot's stream and ended by its event ev_done:
+  // 0 none, 1 upload of B and its norm, 2 a restart cycle, 3 the end of the
+  // request (true residual, download of X)
+  int phase = 0;
 };
 
 // Workspaces of the norm / residual reductions: taken from the context's
@@ -970,6 +979,33 @@ double device_residual(lsba_context* c, const lsba_operator* op, int s, const do
   return c->norm_host[0];
 }
 
+
+// Queue ||x||_F (FP64, fixed order) and its copy to the context's pinned
+// norm_host[slot] without waiting for it.
+void enqueue_norm(lsba_context* c, const double* x, int64_t count, int slot) {
+  double* partial = (double*)ctx_buf(c, "norm_partial",
+                                     sizeof(double) * norm_partial_doubles(count));
+  int nw = 0;
+  launch_sumsq_partial(c->stream, count, x, partial, &nw);
+  double* outd = (double*)ctx_buf(c, "norm_out", sizeof(double) * 4);
+  launch_sumsq_final(c->stream, partial, nw, outd + slot);
+  HIPCHK(hipMemcpyAsync(c->norm_host + slot, outd + slot, sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+}
+
+// Queue ||B - A X||_F (FP64) and its copy to norm_host[slot] without waiting.
+void enqueue_residual_norm(lsba_context* c, const lsba_operator* op, int s, const double* X,
+                           const double* B, int slot) {
+  double* partial = (double*)ctx_buf(c, "res_partial",
+                                     sizeof(double) * res_partial_doubles(op->n, s));
+  int nw = 0;
+  launch_residual(c->stream, op->n, op->nnz, s, op->rp, op->ci, op->val, X, B, nullptr, partial,
+                  &nw, c->timer);
+  double* outd = (double*)ctx_buf(c, "norm_out", sizeof(double) * 4);
+  launch_sumsq_final(c->stream, partial, nw, outd + slot);
+  HIPCHK(hipMemcpyAsync(c->norm_host + slot, outd + slot, sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+}
 
 void validate_params(const lsba_params* p, int s) {
   if (!p) throw ArgError{"params is NULL"};
@@ -1055,8 +1091,9 @@ struct lsba_server {
 
 namespace {
 
-// Admit request r into slot sl: upload B, form ||B||_F, lay out the Krylov
-// state and queue the first cycle.
+// Admit request r into slot sl: queue the upload of B and ||B||_F (phase 1).
+// Nothing here waits for the device: the slot's progress continues in
+// srv_progress once the slot's event has completed.
 void srv_start(lsba_server* sv, SrvSlot& sl, SrvRequest* r) {
   lsba_context* c = sl.c;
   hipStream_t st = c->stream;
@@ -1066,32 +1103,34 @@ void srv_start(lsba_server* sv, SrvSlot& sl, SrvRequest* r) {
   sv->in_use += r->footprint;
   sl.B64 = (double*)ctx_buf(c, "B64", blk64);
   sl.X64 = (double*)ctx_buf(c, "X64", blk64);
-  HIPCHK(hipEventRecord(c->ev0, st));
-  HIPCHK(hipMemcpyAsync(sl.B64, r->B.data(), blk64, hipMemcpyHostToDevice, st));
-  sl.nB = device_norm(c, sl.B64, r->n * r->s);
   r->res->have_loo = (r->p.record & LSBA_REC_LOO) != 0;
-  if (sl.nB == 0.0) {
-    HIPCHK(hipMemsetAsync(sl.X64, 0, blk64, st));
-    r->res->status = LSBA_OK;
-    r->res->true_relres = 0.0;
-    sl.run.reset();
-    HIPCHK(hipEventRecord(c->ev_done, st));
-    sl.in_flight = true;
-    return;
-  }
-  sl.k = make_krylov<double>(c, r->n, r->s, r->p.m, r->p, "d_");
-  sl.run.reset(new CycleRunner<double>{c, r->op, r->p, &sl.k, r->op->val, sl.B64, sl.X64, sl.nB,
-                                       r->p.tol, r->res});
-  sl.run->begin();
-  sl.run->enqueue();
-  sl.in_flight = true;
+  HIPCHK(hipEventRecord(c->ev0, st));
+  HIPCHK(hipMemcpyAsync(sl.B64, r->Bh, blk64, hipMemcpyHostToDevice, st));
+  enqueue_norm(c, sl.B64, r->n * r->s, 0);
+  HIPCHK(hipEventRecord(c->ev_done, st));
+  sl.phase = 1;
 }
 
-// The request in slot sl has ended: copy X out, release the slot's memory.
-void srv_complete(lsba_server* sv, SrvSlot& sl) {
+// Queue the end of the request in slot sl (phase 3): its true residual (if
+// recorded) and the download of X into pinned host memory.
+void srv_finish_enqueue(SrvSlot& sl) {
   lsba_context* c = sl.c;
   SrvRequest* r = sl.req;
   hipStream_t st = c->stream;
+  if (sl.run && (r->p.record & LSBA_REC_TRUE_RES))
+    enqueue_residual_norm(c, r->op, r->s, sl.X64, sl.B64, 1);
+  HIPCHK(hipMemcpyAsync(r->Xh, sl.X64, (size_t)r->n * r->s * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipEventRecord(c->ev1, st));
+  HIPCHK(hipEventRecord(c->ev_done, st));
+  sl.phase = 3;
+}
+
+// The end of the request in slot sl has completed: fill its result, release
+// the slot's memory (stream-ordered), report it.
+void srv_complete(lsba_server* sv, SrvSlot& sl) {
+  lsba_context* c = sl.c;
+  SrvRequest* r = sl.req;
   if (sl.run) {
     const CycleOut& o = sl.run->out;
     r->res->status = o.status;
@@ -1099,55 +1138,61 @@ void srv_complete(lsba_server* sv, SrvSlot& sl) {
     r->res->a = o.a;
     r->res->v = o.v;
     r->res->sy = o.sy;
-    if (r->p.record & LSBA_REC_TRUE_RES)
-      r->res->true_relres = device_residual(c, r->op, r->s, sl.X64, sl.B64, nullptr) / sl.nB;
+    if (r->p.record & LSBA_REC_TRUE_RES) r->res->true_relres = c->norm_host[1] / sl.nB;
   }
-  const size_t blk64 = (size_t)r->n * r->s * sizeof(double);
-  r->X.resize((size_t)r->n * r->s);
-  HIPCHK(hipMemcpyAsync(r->X.data(), sl.X64, blk64, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipEventRecord(c->ev1, st));
-  HIPCHK(hipEventSynchronize(c->ev1));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   r->res->gpu_ms = ms;
   sl.run.reset();
   ctx_release(c);
   sv->in_use -= r->footprint;
-  r->state = 2;
-  r->B.clear();
-  r->B.shrink_to_fit();
+  r->state = 2;   // the pinned copies go with the request at fetch (freeing pinned memory
+                  // may wait for the device, which poll never does)
   sv->done.push_back(r->ticket);
   sl.req = nullptr;
-  sl.in_flight = false;
+  sl.phase = 0;
 }
 
-// One pass of the progress engine: finish cycles whose event has completed
-// and queue the next ones, then admit queued requests in arrival order while
-// a slot is free and the byte budget allows.
+// One pass of the progress engine: advance every slot whose queued work has
+// completed (hipEventQuery, never a wait), then admit queued requests in
+// arrival order while a slot is free and the byte budget allows.
 void srv_progress(lsba_server* sv) {
   for (auto& sl : sv->slots) {
-    if (!sl.req || !sl.in_flight) continue;
+    if (!sl.req || sl.phase == 0) continue;
     const hipError_t q = hipEventQuery(sl.c->ev_done);
     if (q == hipErrorNotReady) {
       (void)hipGetLastError();   // HIP records "not ready" as the thread's last error
       continue;
     }
-    if (q != hipSuccess) throw HipError{std::string("cycle event: ") + hipGetErrorString(q)};
+    if (q != hipSuccess) throw HipError{std::string("slot event: ") + hipGetErrorString(q)};
     HIPCHK(hipGetLastError());
-    sl.in_flight = false;
-    bool end = true;
-    if (sl.run) {
-      end = sl.run->finish();
-      if (!end && sl.run->cyc >= sl.req->p.max_cycles) {
+    SrvRequest* r = sl.req;
+    if (sl.phase == 1) {
+      sl.nB = sl.c->norm_host[0];
+      if (sl.nB == 0.0) {
+        HIPCHK(hipMemsetAsync(sl.X64, 0, (size_t)r->n * r->s * sizeof(double), sl.c->stream));
+        r->res->status = LSBA_OK;
+        r->res->true_relres = 0.0;
+        sl.run.reset();
+        srv_finish_enqueue(sl);
+        continue;
+      }
+      sl.k = make_krylov<double>(sl.c, r->n, r->s, r->p.m, r->p, "d_");
+      sl.run.reset(new CycleRunner<double>{sl.c, r->op, r->p, &sl.k, r->op->val, sl.B64, sl.X64,
+                                           sl.nB, r->p.tol, r->res});
+      sl.run->begin();
+      sl.run->enqueue();
+      sl.phase = 2;
+    } else if (sl.phase == 2) {
+      bool end = sl.run->finish();
+      if (!end && sl.run->cyc >= r->p.max_cycles) {
         sl.run->out.status = LSBA_NOT_CONVERGED;
         end = true;
       }
-    }
-    if (end) {
-      srv_complete(sv, sl);
+      if (end) srv_finish_enqueue(sl);
+      else sl.run->enqueue();
     } else {
-      sl.run->enqueue();
-      sl.in_flight = true;
+      srv_complete(sv, sl);
     }
   }
   while (!sv->queue.empty()) {
@@ -1602,6 +1647,57 @@ lsba_status lsba_context_kernel_flops(const lsba_context* c, int32_t kind, doubl
   return LSBA_OK;
 }
 
+lsba_status lsba_result_set_err_vs_ref(lsba_context* c, lsba_result* r, int64_t n, int32_t s,
+                                       const double* X, int64_t ldx, const double* Xref,
+                                       int64_t ldr, int on_device) {
+  if (!c) return fail(nullptr, LSBA_ERR_ARG, "context is NULL");
+  if (!r || !X || !Xref) return fail(c, LSBA_ERR_ARG, "NULL pointer argument");
+  if (n < 1 || s < 1 || ldx < s || ldr < s) return fail(c, LSBA_ERR_ARG, "bad sizes");
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    const double* Xd = X;
+    const double* Rd = Xref;
+    int64_t lx = ldx, lr = ldr;
+    const size_t blk = (size_t)n * s * sizeof(double);
+    if (!on_device) {
+      double* a = (double*)ctx_buf(c, "cmp_x", blk);
+      double* b = (double*)ctx_buf(c, "cmp_ref", blk);
+      HIPCHK(hipMemcpy2DAsync(a, s * sizeof(double), X, ldx * sizeof(double), s * sizeof(double),
+                              n, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpy2DAsync(b, s * sizeof(double), Xref, ldr * sizeof(double),
+                              s * sizeof(double), n, hipMemcpyHostToDevice, st));
+      Xd = a;
+      Rd = b;
+      lx = lr = s;
+    }
+    double* partial = (double*)ctx_buf(c, "cmp_partial",
+                                       sizeof(double) * norm_partial_doubles((int64_t)n * s));
+    double* outd = (double*)ctx_buf(c, "norm_out", sizeof(double) * 4);
+    int nw = 0;
+    launch_diff_sumsq_partial(st, n, s, Xd, lx, Rd, lr, partial, &nw);
+    launch_sumsq_final(st, partial, nw, outd);
+    HIPCHK(hipMemcpyAsync(c->norm_host, outd, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double dn = c->norm_host[0];
+    // ||Xref||_F over contiguous rows
+    const double* Rc = Rd;
+    if (lr != s) {
+      double* b = (double*)ctx_buf(c, "cmp_ref", blk);
+      HIPCHK(hipMemcpy2DAsync(b, s * sizeof(double), Rd, lr * sizeof(double), s * sizeof(double),
+                              n, hipMemcpyDeviceToDevice, st));
+      Rc = b;
+    }
+    const double rn = device_norm(c, Rc, (int64_t)n * s);
+    r->err_vs_ref = rn > 0.0 ? dn / rn : dn;
+  } catch (const HipError& e) {
+    return fail(c, LSBA_ERR_HIP, e.msg);
+  }
+  return LSBA_OK;
+}
+
+double lsba_result_err_vs_ref(const lsba_result* r) { return r ? r->err_vs_ref : NAN; }
+
 lsba_status lsba_result_status(const lsba_result* r) { return r ? r->status : LSBA_ERR_ARG; }
 int64_t lsba_result_iters(const lsba_result* r) { return r ? r->iters : 0; }
 const double* lsba_result_res_hist(const lsba_result* r) {
@@ -1686,19 +1782,20 @@ lsba_status lsba_server_submit(lsba_server* sv, const lsba_operator* op, const l
   r->n = op->n;
   r->footprint = fp;
   try {
-    r->B.resize((size_t)r->n * s);
     HIPCHK(hipSetDevice(c->device));
-    HIPCHK(hipMemcpy2D(r->B.data(), s * sizeof(double), B, ldb * sizeof(double),
-                       s * sizeof(double), r->n,
-                       on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+    const size_t blk = (size_t)r->n * s * sizeof(double);
+    if (hipHostMalloc((void**)&r->Bh, blk, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&r->Xh, blk, hipHostMallocDefault) != hipSuccess) {
+      delete r->res;
+      delete r;
+      return fail(c, LSBA_ERR_OOM, "pinned host allocation failed");
+    }
+    HIPCHK(hipMemcpy2D(r->Bh, s * sizeof(double), B, ldb * sizeof(double), s * sizeof(double),
+                       r->n, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
   } catch (const HipError& e) {
     delete r->res;
     delete r;
     return fail(c, LSBA_ERR_HIP, e.msg);
-  } catch (const std::bad_alloc&) {
-    delete r->res;
-    delete r;
-    return fail(c, LSBA_ERR_OOM, "host allocation failed");
   }
   r->ticket = sv->next_ticket++;
   sv->reqs[r->ticket] = r;
@@ -1738,7 +1835,7 @@ lsba_status lsba_server_fetch(lsba_server* sv, uint64_t ticket, double* X, int64
   if (ldx < r->s) return fail(c, LSBA_ERR_ARG, "ldx must be >= s");
   try {
     HIPCHK(hipSetDevice(c->device));
-    HIPCHK(hipMemcpy2D(X, ldx * sizeof(double), r->X.data(), r->s * sizeof(double),
+    HIPCHK(hipMemcpy2D(X, ldx * sizeof(double), r->Xh, r->s * sizeof(double),
                        r->s * sizeof(double), r->n,
                        on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
   } catch (const HipError& e) {

@@ -35,7 +35,8 @@ EXPORTS = [
     "lsba_result_destroy", "lsba_context_set_timing", "lsba_context_kernel_stats",
     "lsba_solve_footprint", "lsba_server_create", "lsba_server_submit", "lsba_server_poll",
     "lsba_server_fetch", "lsba_server_stats", "lsba_server_destroy", "lsba_context_set_graphs",
-    "lsba_solve_noalloc", "lsba_context_kernel_flops",
+    "lsba_solve_noalloc", "lsba_context_kernel_flops", "lsba_result_set_err_vs_ref",
+    "lsba_result_err_vs_ref",
 ]
 
 KERNEL_KINDS = {"spmm": 0, "gram": 1, "gram_reduce": 2, "update": 3, "small": 4, "residual": 5}
@@ -127,6 +128,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
                                       ctypes.POINTER(i64)]),
         "lsba_result_true_relres": (dbl, [vp]),
         "lsba_result_refine_steps": (i32, [vp]),
+        "lsba_result_set_err_vs_ref": (i32, [vp, vp, i64, i32, vp, i64, vp, i64, ctypes.c_int]),
+        "lsba_result_err_vs_ref": (dbl, [vp]),
         "lsba_result_gpu_ms": (dbl, [vp]),
         "lsba_result_destroy": (None, [vp]),
         "lsba_context_set_timing": (i32, [vp, ctypes.c_uint32]),
@@ -285,6 +288,7 @@ class Result:
     true_relres: float
     refine_steps: int
     gpu_ms: float
+    err_vs_ref: float = float("nan")
 
 
 def make_params(method="gmres", skeleton="bcgsi_ls", muscle="cholqr", precision="fp64", m=20,
@@ -309,9 +313,11 @@ def make_params(method="gmres", skeleton="bcgsi_ls", muscle="cholqr", precision=
     return p
 
 
-def solve(ctx: Context, op: Operator, B, X=None, **kw) -> Result:
+def solve(ctx: Context, op: Operator, B, X=None, x_ref=None, **kw) -> Result:
     """Solve A X = B (B: n x s, row-major NumPy array or torch CUDA tensor).
-    Keyword arguments are those of ``make_params``."""
+    Keyword arguments are those of ``make_params``.  ``x_ref``: a reference
+    solution (same kind of array as B, e.g. the FP64 oracle's X); the result
+    then carries ||X - x_ref||_F / ||x_ref||_F, formed by the library."""
     lib = ctx.lib
     p = make_params(**kw)
     on_dev = _is_torch(B)
@@ -336,6 +342,18 @@ def solve(ctx: Context, op: Operator, B, X=None, **kw) -> Result:
                         1 if on_dev else 0, ctypes.byref(h))
     if st < 0:
         raise LsbaError(st, ctx.error())
+    if x_ref is not None:
+        if on_dev:
+            assert x_ref.shape == B.shape and x_ref.stride(1) == 1
+            rptr, ldr = ctypes.c_void_p(x_ref.data_ptr()), x_ref.stride(0)
+        else:
+            x_ref = np.ascontiguousarray(x_ref, dtype=np.float64)
+            rptr, ldr = x_ref.ctypes.data_as(ctypes.c_void_p), s
+        st2 = lib.lsba_result_set_err_vs_ref(ctx.h, h, n, s, xptr, ldx, rptr, ldr,
+                                             1 if on_dev else 0)
+        if st2 < 0:
+            lib.lsba_result_destroy(h)
+            raise LsbaError(st2, ctx.error())
     return _take_result(lib, h, X)
 
 
@@ -376,7 +394,8 @@ def _take_result(lib, h, X) -> Result:
                       m_after=list(ma[:nc]) if nc else [], counts=(a.value, v.value, sy.value),
                       true_relres=lib.lsba_result_true_relres(h),
                       refine_steps=lib.lsba_result_refine_steps(h),
-                      gpu_ms=lib.lsba_result_gpu_ms(h))
+                      gpu_ms=lib.lsba_result_gpu_ms(h),
+                      err_vs_ref=lib.lsba_result_err_vs_ref(h))
     finally:
         lib.lsba_result_destroy(h)
 
