@@ -68,3 +68,36 @@ def test_laplace3d_128_first_iteration_matches_oracle():
     o = oracle_solve(wl.A, wl.B, "gmres", "bcgsi_ls", m=wl.m, tol=wl.tol,
                      max_cycles=wl.max_cycles, max_iters=1)
     assert_parity(g, o, hist_atol=1e-11)
+
+
+def test_laplace3d_16cube_complete_solve_matches_oracle():
+    """The 3-D workload's construction at 16^3 (n = 4096) with its block size
+    and restart length (s = 32, m = 20, tol 1e-10): a complete BGMRES solve,
+    every cycle, compared with the oracle (same iteration count and restart
+    points, X to 1e-10)."""
+    wl = w.workload("laplace3d", scale=16)
+    g = gpu_solve(wl.A, wl.B, method="gmres", skeleton="bcgsi_ls", m=wl.m, tol=wl.tol,
+                  max_cycles=wl.max_cycles, true_res=True)
+    o = oracle_solve(wl.A, wl.B, "gmres", "bcgsi_ls", m=wl.m, tol=wl.tol,
+                     max_cycles=wl.max_cycles)
+    assert o.status == "ok" and len(o.cycle_len) >= 2
+    assert_parity(g, o, hist_atol=1e-12)
+
+
+def test_rgg_2pow14_capped_solve_matches_oracle():
+    """The random-geometric-graph workload's construction at n = 2^14 with
+    its block size and restart length (s = 16, m = 25): 150 block iterations
+    (six cycles), every one compared with the oracle: same counts and
+    restart points, histories to 10 u kappa (kappa ~ 1e6, the 1e-6 shift).
+    The iterate is far from converged (relative residual 0.25), and its
+    coefficients solve projected problems as ill-conditioned as A
+    (kappa(H_j) up to ~1e6) from Gram entries that differ in the last bits:
+    X is compared to 1e-5 (kappa(H) times the 1e-11 agreement of the
+    projected data), the histories carry the tight check."""
+    wl = w.workload("rgg", scale=1 << 14)
+    g = gpu_solve(wl.A, wl.B, method="gmres", skeleton="bcgsi_ls", m=wl.m, tol=wl.tol,
+                  max_cycles=wl.max_cycles, max_iters=150)
+    o = oracle_solve(wl.A, wl.B, "gmres", "bcgsi_ls", m=wl.m, tol=wl.tol,
+                     max_cycles=wl.max_cycles, max_iters=150)
+    assert len(o.cycle_len) == 6
+    assert_parity(g, o, x_tol=1e-5, hist_atol=1e-9)

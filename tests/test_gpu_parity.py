@@ -137,3 +137,53 @@ def test_paper_tridiag_counts_on_gpu():
         assert np.linalg.norm(g.X - o.X) / np.linalg.norm(o.X) <= 1e-10
         h, ho = np.asarray(g.res_hist[:6]), np.asarray(o.res_hist[:6])
         assert np.all(np.abs(h - ho) <= 1e-8 * ho)
+
+
+@pytest.mark.parametrize("skel", ["bcgsi_ls", "bmgs_cwy", "bmgs_svl"])
+def test_loss_of_orthogonality_above_rounding(skel):
+    """LOO well above rounding: the right-hand side has two nearly dependent
+    columns (kappa(B) ~ 1.9e4), so CholQR's orthogonality error, about
+    u kappa(B)^2, puts the first cycle's LOO at 6e-8 .. 4e-6 (oracle).  The
+    value is a rounding error amplified by kappa(B)^2: its size, not its
+    digits, is determined, so GPU and oracle must agree within a factor of 4
+    at every column of the first cycle (both >= 1e-8).  Later cycles restart
+    from the well-conditioned block U, where both must be back at rounding
+    level (< 1e-12); the solves themselves match as in the other parity
+    tests."""
+    A = w.laplace_2d(20)
+    B = w.rhs(A.n, 4, 21)
+    B[:, 1] = B[:, 0] + 1e-4 * B[:, 1]
+    g = gpu_solve(A, B, method="gmres", skeleton=skel, m=10, tol=1e-8, max_cycles=50,
+                  record_loo=True)
+    o = oracle_solve(A, B, "gmres", skel, m=10, tol=1e-8, max_cycles=50, record_loo=True)
+    # with LOO up to 4e-6 the estimates carry that orthogonality error: their
+    # last digits below ~1e-9 depend on rounding (differences of 1.6e-10 were
+    # seen at the 1e-10 level), so the solve stops at 1e-8 and the history
+    # is compared to 1e-9 absolute
+    assert_parity(g, o, x_tol=1e-8, hist_atol=1e-9)
+    lg, lo = np.asarray(g.loo_hist), np.asarray(o.loo_hist)
+    assert lg.shape == lo.shape
+    c1 = g.cycle_len[0]
+    f_g, f_o = lg[:c1], lo[:c1]
+    assert np.all(f_o >= 1e-8) and np.all(f_g >= 1e-8)
+    ratio = f_g / f_o
+    assert np.all((ratio > 0.25) & (ratio < 4.0)), (ratio.min(), ratio.max())
+    rest_g, rest_o = lg[c1:], lo[c1:]
+    ok = ~np.isnan(rest_g)
+    assert ok.sum() >= rest_g.size - 1
+    assert np.all(rest_g[ok] < 1e-12) and np.all(rest_o[ok] < 1e-12)
+
+
+def test_err_vs_ref_reports_error_against_the_oracle():
+    """lsba_result_set_err_vs_ref / lsba_result_err_vs_ref: the library's
+    ||X - X_oracle||_F / ||X_oracle||_F equals the same quantity formed in
+    NumPy from the returned X (host arrays), and the FP64 form's error is
+    within the parity bound."""
+    A = w.convdiff_2d(30, 4.0, 0.7)
+    B = w.rhs(A.n, 4, 31)
+    o = oracle_solve(A, B, "gmres", "bcgsi_ls", m=15, tol=1e-10, max_cycles=100)
+    g = gpu_solve(A, B, method="gmres", skeleton="bcgsi_ls", m=15, tol=1e-10, max_cycles=100,
+                  x_ref=o.X)
+    ref = np.linalg.norm(np.asarray(g.X) - o.X) / np.linalg.norm(o.X)
+    assert abs(g.err_vs_ref - ref) <= 1e-12 * max(ref, 1e-300) + 1e-18
+    assert g.err_vs_ref <= 1e-10
