@@ -34,6 +34,9 @@ if ROOT not in sys.path:
 METRIC = "block-Arnoldi GB/s + solves/s at rel. residual 1e-8; serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6       # MI355X dense FP64 matrix / vector peak (published)
+FP32_PEAK_TFS = 157.3      # MI355X FP32 vector peak (published)
+BF16_PEAK_TFS = 2500.0     # MI355X dense BF16 matrix peak (published, no sparsity)
+BF16_SPLIT_PRODUCTS = 6    # FP32 products as six BF16 part products (three-part splits)
 
 WORKLOADS = {
     # name: (workload key, scale, solve list [(method, skeleton)], precision, s, note)
@@ -308,14 +311,24 @@ def main():
         launches, ms, by = live[dom]
         fl = live_flops[dom]
         # roofline of the dominant class: the time its launches need at the
-        # HBM peak or at the FP64 peak, whichever is longer, over the time
-        # they took (per-launch bytes and flops grow together, so the sums
-        # decide the bound as the single launches do)
+        # HBM peak or at the arithmetic peak of the units they run on,
+        # whichever is longer, over the time they took (per-launch bytes and
+        # flops grow together, so the sums decide the bound as the single
+        # launches do).  FP64 kernels: the FP64 peak.  FP32 Gram / update at
+        # s = 16, 32: BF16 matrix cores, six part products per FP32 product,
+        # so the algorithmic FP32 flops are priced at 2.5 PFLOP/s / 6.
+        if precision == "fp64":
+            peak_tfs, peak_note = FP64_PEAK_TFS, "FP64 dense peak"
+        elif s in (16, 32) and dom in ("gram", "update"):
+            peak_tfs = BF16_PEAK_TFS / BF16_SPLIT_PRODUCTS
+            peak_note = "FP32 products as six BF16 matrix-core products: 2500 / 6 TFLOP/s"
+        else:
+            peak_tfs, peak_note = FP32_PEAK_TFS, "FP32 vector peak"
         t_b = by / (HBM_PEAK_GBS * 1e9)
-        t_f = fl / (FP64_PEAK_TFS * 1e12)
+        t_f = fl / (peak_tfs * 1e12)
         sec = ms * 1e-3
         if t_f > t_b:
-            bound, achieved, peak, unit = "mfma", fl / sec / 1e12, FP64_PEAK_TFS, "TFLOP/s"
+            bound, achieved, peak, unit = "mfma", fl / sec / 1e12, peak_tfs, "TFLOP/s"
         else:
             bound, achieved, peak, unit = "hbm", by / sec / 1e9, HBM_PEAK_GBS, "GB/s"
         line["roofline"] = {
@@ -327,7 +340,9 @@ def main():
             "frac": achieved / peak,
             "traffic": None,
             "hbm_gbs": by / sec / 1e9 if sec else None,
-            "fp64_tflops": fl / sec / 1e12 if sec else None,
+            "alg_tflops": fl / sec / 1e12 if sec else None,
+            "flops_peak_tfs": peak_tfs,
+            "flops_peak_note": peak_note,
             "avg_launch_us": 1e3 * ms / launches if launches else None,
             "alg_bytes_per_launch": by / launches if launches else None,
             "alg_flops_per_launch": fl / launches if launches else None,

@@ -378,6 +378,252 @@ __global__ __launch_bounds__(512) void gram_mfma_wide(GramArgs<T> a, int nchunk,
           out[(int64_t)((st0 + i) * 16 + 4 * q + lk) * QB + j * 16 + lr] = acc[i][j][q];
 }
 
+// FP32 Gram for s = 16, 32 on the BF16 matrix cores with FP32 accumulation
+// (the precision form's inner solves).  Each FP32 value x is split into
+// three bfloat16 parts x = h + m + l (each the round-to-nearest of what is
+// left; 24 significant bits, like FP32) and each product takes the six part
+// products down to 2^-16 relative size (l*h, h*l, m*m, m*h, h*m, h*h; the
+// dropped ones are below 2^-24), so the Gram keeps FP32 accuracy at the
+// BF16 matrix rate.  The contraction runs over rows and
+// v_mfma_f32_16x16x32_bf16 wants each lane to hold eight consecutive K
+// values: lane l takes column l % 16 of a 16-column strip (A) or tile (B)
+// at rows 8 (l / 16) .. 8 (l / 16) + 7.  Row-major blocks do not store
+// those together, so a workgroup stages a tile of 32 rows of its left
+// blocks and of the right blocks in LDS, split into the three bf16 planes
+// and stored column-major: column c of a block keeps its 32 rows in four
+// 8-row groups, group g at slot g ^ ((c / 4) mod 4), which puts the
+// 16-byte reads of the 16 lanes of a row group in 16 distinct bank
+// quarters.  Each thread loads two rows of four columns (two 16-byte
+// loads, consecutive threads on consecutive columns), converts each
+// column's pair of rows to one packed bf16 word per plane and writes it;
+// the tile after next is in flight in registers meanwhile, and LDS is
+// double-buffered, one barrier per tile.  Wavefronts split the workgroup's
+// 16-column strips (at most 3 each) and take every right tile; partials
+// (FP32 per chunk, summed in FP64 across chunks) go to partial[chunk] as
+// for the other stage-1 kernels.
+constexpr int kBTR = 32;             // rows per staged tile
+constexpr int kBMaxBlk = 10;         // s = 32 blocks (left + right) staged per workgroup
+constexpr int kBSW = 3;              // strips per wavefront at most
+constexpr int kBPlaneShorts = kBMaxBlk * 32 * kBTR;   // one plane of one buffer
+
+typedef short bs8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bb8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bb2 __attribute__((ext_vector_type(2)));
+typedef float bf4acc __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf4acc bmfma(bs8 a, bs8 b, bf4acc c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bb8, a),
+                                                 __builtin_bit_cast(bb8, b), c, 0, 0, 0);
+}
+
+// Two FP32 values (consecutive rows of one column) to three packed bf16
+// words, parts h, m, l in that order; the conversions round to nearest even.
+__device__ __forceinline__ void bsplit3_pair(float x0, float x1, unsigned& h, unsigned& m,
+                                             unsigned& l) {
+  bb2 p;
+  p[0] = (__bf16)x0;
+  p[1] = (__bf16)x1;
+  h = __builtin_bit_cast(unsigned, p);
+  const float r0 = x0 - __uint_as_float(h << 16), r1 = x1 - __uint_as_float(h & 0xFFFF0000u);
+  p[0] = (__bf16)r0;
+  p[1] = (__bf16)r1;
+  m = __builtin_bit_cast(unsigned, p);
+  p[0] = (__bf16)(r0 - __uint_as_float(m << 16));
+  p[1] = (__bf16)(r1 - __uint_as_float(m & 0xFFFF0000u));
+  l = __builtin_bit_cast(unsigned, p);
+}
+
+// short offset of (column c, row r) inside a block's plane slice
+__device__ __forceinline__ int bswz(int c, int r) {
+  return c * kBTR + 8 * ((r >> 3) ^ ((c >> 2) & 3)) + (r & 7);
+}
+
+template <int NTR>
+__global__ __launch_bounds__(512) void gram_bf16(GramArgs<float> a, int nchunk, int ngroup,
+                                                 int nlb_max, int64_t rows_per_chunk,
+                                                 double* __restrict__ partial,
+                                                 const Ctl* __restrict__ ctl) {
+  constexpr int TR = kBTR;
+  __shared__ __align__(16) short lds[2][3][kBPlaneShorts];
+  if (ctl && ctl->stop) return;
+  const int pid = blockIdx.x;
+  const int xcd = pid % kXcds, t = pid / kXcds;
+  const int chunk = xcd + kXcds * (t / ngroup);
+  const int grp = t % ngroup;
+  if (chunk >= nchunk) return;
+  const int s = a.s;
+  const int NBL = a.nv + a.nxl;
+  const int PA = NBL * s, QB = a.nxr * s;
+  const int lb0 = grp * nlb_max;
+  const int nlb = NBL - lb0 < nlb_max ? NBL - lb0 : nlb_max;
+  if (nlb <= 0) return;
+  const int nbs = nlb + a.nxr;                 // blocks staged
+  const int bsz = s * TR;                      // shorts per block in one plane
+  const int spb = s >> 4;                      // strips per block
+  const int NS = nlb * spb;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int base = NS / 8, extra = NS % 8;
+  const int st0 = wave * base + (wave < extra ? wave : extra);
+  const int nsw = base + (wave < extra ? 1 : 0);
+  const int lc = lane & 15, lk = lane >> 4;
+  const int64_t r0 = (int64_t)chunk * rows_per_chunk;
+  const int64_t r1 = r0 + rows_per_chunk < a.n ? r0 + rows_per_chunk : a.n;
+  const int nst = (int)((r1 - r0 + TR - 1) / TR);
+  // staging unit e = (block, row pair, 4-column group); a thread's units
+  // and their addresses are fixed for the whole chunk
+  const int cpr = s >> 2;
+  const int upb = (TR / 2) * cpr;
+  const int nunit = nbs * upb;
+  constexpr int UPT = (kBMaxBlk * 32 * TR / 8 + 511) / 512;
+  typedef float fq4 __attribute__((ext_vector_type(4)));
+  const float* gb[UPT];     // row r0 of the unit's block, its first column
+  int rp2[UPT], lw[UPT];    // first row of the pair; LDS word of its first column
+#pragma unroll
+  for (int u = 0; u < UPT; ++u) {
+    const int e = threadIdx.x + 512 * u;
+    const int blk = e < nunit ? e / upb : 0, rem = e % upb;
+    const int rp = e < nunit ? rem / cpr : 0, c4 = e < nunit ? rem % cpr : 0;
+    const float* bp = blk < nlb ? left_ptr(a, lb0 + blk) : a.xr[blk - nlb];
+    gb[u] = bp + r0 * s + 4 * c4;
+    rp2[u] = 2 * rp;
+    lw[u] = e < nunit ? (blk * bsz + bswz(4 * c4, 2 * rp)) >> 1 : -1;
+  }
+  // every thread issues the same loads for every tile (inactive units and
+  // rows past the chunk read a valid row), so the waits on them are static;
+  // the rows past the chunk are zeroed only when the tile is stored
+  auto gload = [&](fq4 (&ra)[UPT], fq4 (&rb)[UPT], int st) {
+    const int lim = (int)(r1 - r0) - st * TR;          // rows of this tile in the chunk
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+      const float* p0 = gb[u] + (int64_t)(rp2[u] < lim ? st * TR + rp2[u] : 0) * s;
+      const float* p1 = gb[u] + (int64_t)(rp2[u] + 1 < lim ? st * TR + rp2[u] + 1 : 0) * s;
+      ra[u] = *reinterpret_cast<const fq4*>(p0);
+      rb[u] = *reinterpret_cast<const fq4*>(p1);
+    }
+  };
+  auto lstore = [&](int buf, const fq4 (&ra)[UPT], const fq4 (&rb)[UPT], int st) {
+    unsigned* H = reinterpret_cast<unsigned*>(&lds[buf][0][0]);
+    unsigned* M = reinterpret_cast<unsigned*>(&lds[buf][1][0]);
+    unsigned* L = reinterpret_cast<unsigned*>(&lds[buf][2][0]);
+    const int lim = (int)(r1 - r0) - st * TR;
+#pragma unroll
+    for (int u = 0; u < UPT; ++u)
+      if (lw[u] >= 0) {
+        const bool ok0 = rp2[u] < lim, ok1 = rp2[u] + 1 < lim;   // rows past r1 contribute 0
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int w = lw[u] + (kBTR / 2) * q;
+          unsigned h, m, l;
+          bsplit3_pair(ok0 ? ra[u][q] : 0.f, ok1 ? rb[u][q] : 0.f, h, m, l);
+          H[w] = h;
+          M[w] = m;
+          L[w] = l;
+        }
+      }
+  };
+  bf4acc acc[kBSW][NTR];
+#pragma unroll
+  for (int i = 0; i < kBSW; ++i)
+#pragma unroll
+    for (int j = 0; j < NTR; ++j) acc[i][j] = bf4acc{0.f, 0.f, 0.f, 0.f};
+  // lane's operand: column c of block blk, rows 8 lk .. 8 lk + 7, one plane
+  auto opnd = [&](const short* P, int blk, int c) {
+    return *reinterpret_cast<const bs8*>(P + blk * bsz + bswz(c, 8 * lk));
+  };
+  auto compute = [&](int buf) {
+    const short* Ph = &lds[buf][0][0];
+    const short* Pm = &lds[buf][1][0];
+    const short* Pl = &lds[buf][2][0];
+    bs8 bh[NTR], bm[NTR], bl[NTR];
+#pragma unroll
+    for (int j = 0; j < NTR; ++j) {
+      const int col = 16 * j + lc;
+      const int blk = nlb + col / s, c = col % s;
+      bh[j] = opnd(Ph, blk, c);
+      bm[j] = opnd(Pm, blk, c);
+      bl[j] = opnd(Pl, blk, c);
+    }
+#pragma unroll
+    for (int i = 0; i < kBSW; ++i)
+      if (i < nsw) {
+        const int strip = st0 + i;
+        const int blk = strip / spb, c = (strip % spb) * 16 + lc;
+        const bs8 ah = opnd(Ph, blk, c), am = opnd(Pm, blk, c), al = opnd(Pl, blk, c);
+#pragma unroll
+        for (int j = 0; j < NTR; ++j) {
+          bf4acc x = acc[i][j];
+          x = bmfma(al, bh[j], x);
+          x = bmfma(ah, bl[j], x);
+          x = bmfma(am, bm[j], x);
+          x = bmfma(am, bh[j], x);
+          x = bmfma(ah, bm[j], x);
+          x = bmfma(ah, bh[j], x);
+          acc[i][j] = x;
+        }
+      }
+  };
+  // Pipeline: at the top of step st, LDS buffer st & 1 holds tile st and
+  // the two register sets hold tiles st + 1 and st + 2 in flight (tile
+  // numbers past the last clamp to it: a re-read, never out of range).
+  fq4 xa[UPT], xb[UPT], ya[UPT], yb[UPT];
+  const int last = nst - 1;
+  gload(xa, xb, 0);
+  gload(ya, yb, last < 1 ? last : 1);
+  lstore(0, xa, xb, 0);
+  gload(xa, xb, last < 2 ? last : 2);
+  __syncthreads();
+  for (int st = 0; st < nst; st += 2) {
+    // tile st + 1 in y, tile st + 2 in x
+    compute(0);
+    if (st + 1 < nst) lstore(1, ya, yb, st + 1);
+    gload(ya, yb, st + 3 < last ? st + 3 : last);
+    __syncthreads();
+    if (st + 1 >= nst) break;
+    // tile st + 2 in x, tile st + 3 in y
+    compute(1);
+    if (st + 2 < nst) lstore(0, xa, xb, st + 2);
+    gload(xa, xb, st + 4 < last ? st + 4 : last);
+    __syncthreads();
+  }
+  // D layout: lane l holds rows 4 (l / 16) + r of column l % 16
+  double* out = partial + (int64_t)chunk * PA * QB;
+  const int col0 = lb0 * s;
+#pragma unroll
+  for (int i = 0; i < kBSW; ++i)
+    if (i < nsw)
+#pragma unroll
+      for (int j = 0; j < NTR; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          out[(int64_t)(col0 + (st0 + i) * 16 + 4 * lk + r) * QB + 16 * j + lc] =
+              (double)acc[i][j][r];
+}
+
+// Plan of gram_bf16: the left blocks split into ngroup ranges so that at
+// most kBMaxBlk s = 32 blocks (twice as many s = 16 ones) are staged per
+// workgroup; one workgroup per CU (LDS), so the chunks make two full rounds
+// of 256 workgroups; chunks a multiple of 32 rows.
+struct BPlan {
+  int ntr, nlb_max, ngroup, nchunk;
+  int64_t rows;
+};
+
+BPlan bplan(int64_t n, int s, int PA, int QB) {
+  BPlan p;
+  p.ntr = QB / 16;
+  const int nbl = PA / s, nbr = QB / s;
+  const int cap = kBMaxBlk * (32 / s) - nbr;
+  p.ngroup = (nbl + cap - 1) / cap;
+  p.nlb_max = (nbl + p.ngroup - 1) / p.ngroup;
+  int64_t nchunk = (512 / p.ngroup) / kXcds * kXcds;
+  const int64_t maxc = (n + 511) / 512;
+  if (nchunk > maxc) nchunk = maxc;
+  if (nchunk < 1) nchunk = 1;
+  p.rows = (((n + nchunk - 1) / nchunk) + kBTR - 1) / kBTR * kBTR;
+  p.nchunk = (int)((n + p.rows - 1) / p.rows);
+  return p;
+}
+
 struct MPlan {
   int nchunk, ngroup;
   int64_t rows;
@@ -397,6 +643,8 @@ struct WPlan {
 };
 
 bool use_wide(int s, int QB) { return s % 16 == 0 && (QB == 16 || QB == 32 || QB == 64); }
+// gram_bf16 covers FP32 blocks of s = 16 or 32 (its staging sizes assume it)
+bool use_bf16(int s, int QB) { return (s == 16 || s == 32) && use_wide(s, QB); }
 
 WPlan wplan(int64_t n, int PA, int QB) {
   WPlan p;
@@ -476,6 +724,11 @@ size_t gram_partial_doubles(int64_t n, int s, int nleft, int nright) {
         const size_t nm = (size_t)q.nchunk * (size_t)(nl * s) * (size_t)(nr * s);
         if (nm > need) need = nm;
       }
+      if (use_bf16(s, nr * s)) {
+        const BPlan qb = bplan(n, s, nl * s, nr * s);
+        const size_t nb = (size_t)qb.nchunk * (size_t)(nl * s) * (size_t)(nr * s);
+        if (nb > need) need = nb;
+      }
       if (use_wide(s, nr * s)) {
         const WPlan q = wplan(n, nl * s, nr * s);
         const size_t nm = (size_t)q.nchunk * (size_t)(nl * s) * (size_t)(nr * s);
@@ -515,6 +768,25 @@ void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* 
                  const Ctl* ctl, KTimer* tm) {
   const int PA = (a.nv + a.nxl) * a.s, QB = a.nxr * a.s;
   const double gflops = 2.0 * (double)a.n * PA * QB;
+  if constexpr (sizeof(T) == sizeof(float)) {
+    if (use_bf16(a.s, QB)) {
+      const BPlan q = bplan(a.n, a.s, PA, QB);
+      const int nchunk_pad = ((q.nchunk + kXcds - 1) / kXcds) * kXcds;
+      const dim3 g(nchunk_pad * q.ngroup), b(512);
+      const double bytes = (double)distinct_blocks(a) * a.n * a.s * sizeof(T);
+      if (q.ntr == 4)
+        launch_kf(tm, KK_GRAM, bytes, gflops, gram_bf16<4>, g, b, 0, st, a, q.nchunk, q.ngroup,
+                  q.nlb_max, q.rows, partial, ctl);
+      else if (q.ntr == 2)
+        launch_kf(tm, KK_GRAM, bytes, gflops, gram_bf16<2>, g, b, 0, st, a, q.nchunk, q.ngroup,
+                  q.nlb_max, q.rows, partial, ctl);
+      else
+        launch_kf(tm, KK_GRAM, bytes, gflops, gram_bf16<1>, g, b, 0, st, a, q.nchunk, q.ngroup,
+                  q.nlb_max, q.rows, partial, ctl);
+      launch_stage2(st, partial, q.nchunk, PA * QB, out, ctl, tm);
+      return;
+    }
+  }
   if (use_wide(a.s, QB)) {
     {
       const WPlan q = wplan(a.n, PA, QB);

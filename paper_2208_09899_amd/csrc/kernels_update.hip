@@ -442,11 +442,12 @@ __global__ __launch_bounds__(512) void update_mfma_wide(UpdateArgs<double> a,
 }
 
 // FP32 blocks, s = 16 or 32, on the BF16 matrix cores with FP32
-// accumulation: every FP32 operand x is split into bf16 parts
-// x = hi + lo (hi = x rounded to bfloat16, lo = the rounded remainder), and
-// each product takes hi*hi + hi*lo + lo*hi (the dropped lo*lo is below
-// 2^-16 relative), so the update keeps close to FP32 accuracy at the BF16
-// matrix rate.  Product shape as in update_mfma_wide: [out1 | out2] = the
+// accumulation: every FP32 operand x is split into three bf16 parts
+// x = h + m + l (h = x rounded to bfloat16, m the rounded remainder, l the
+// rounded remainder of that; 24 significant bits in all, like FP32), and
+// each product takes the six part products down to 2^-16 relative size
+// (l*h, h*l, m*m, m*h, h*m, h*h, smallest first; the dropped ones are below
+// 2^-24), so the update keeps FP32 accuracy at the BF16 matrix rate.  Product shape as in update_mfma_wide: [out1 | out2] = the
 // input rows times the stacked coefficient rows, one K = s product per
 // input block and 16-column output tile (v_mfma_f32_16x16x32_bf16 for
 // s = 32, v_mfma_f32_16x16x16bf16_1k for s = 16): lane l holds row l % 16
@@ -454,7 +455,7 @@ __global__ __launch_bounds__(512) void update_mfma_wide(UpdateArgs<double> a,
 // or two 16-byte loads), the coefficient fragment holds the same rows of
 // the coefficient block, and the result rows 4 (l / 16) + r of column l % 16.
 // A workgroup of 8 wavefronts owns 256 rows; each input's coefficient
-// fragments, already split into bf16 hi / lo, are staged in LDS once per
+// fragments, already split into the three bf16 parts, are staged in LDS once per
 // workgroup, double-buffered; the next input's rows load while the current
 // one is multiplied.
 typedef short us8 __attribute__((ext_vector_type(8)));
@@ -471,11 +472,14 @@ __device__ __forceinline__ unsigned short bf16_bits(float x) {
 __device__ __forceinline__ float bf16_value(unsigned short b) {
   return __uint_as_float((unsigned int)b << 16);
 }
-// x = hi + lo with hi, lo bfloat16 (bit patterns)
-__device__ __forceinline__ void bf16_split(float x, short& hi, short& lo) {
-  const unsigned short h = bf16_bits(x);
-  hi = (short)h;
-  lo = (short)bf16_bits(x - bf16_value(h));
+// x = h + m + l with h, m, l bfloat16 (bit patterns)
+__device__ __forceinline__ void bf16_split3(float x, short& h, short& m, short& l) {
+  const unsigned short hb = bf16_bits(x);
+  const float r1 = x - bf16_value(hb);
+  const unsigned short mb = bf16_bits(r1);
+  h = (short)hb;
+  m = (short)mb;
+  l = (short)bf16_bits(r1 - bf16_value(mb));
 }
 
 template <int KPL>
@@ -507,8 +511,8 @@ __global__ __launch_bounds__(512) void update_bf16x3(UpdateArgs<float> a,
   constexpr int NT = 2 * S / 16;    // output tiles of 16 columns
   constexpr int KPL = S / 4;        // input columns per lane
   constexpr int RG = 2;             // row groups of 16 per wavefront
-  constexpr int FR = NT * 64 * KPL; // bf16 values of one part (hi or lo) of an input's fragments
-  __shared__ short cf[2][2][FR];    // [buffer][hi / lo][tile][lane][KPL]
+  constexpr int FR = NT * 64 * KPL; // bf16 values of one part of an input's fragments
+  __shared__ short cf[2][3][FR];    // [buffer][h / m / l][tile][lane][KPL]
   if (obey_stop && ctl && ctl->stop) return;
   int nv1 = a.nv1, nb = a.nv2_begin, nv2 = a.nv2;
   if (a.nvp) {
@@ -576,10 +580,11 @@ __global__ __launch_bounds__(512) void update_bf16x3(UpdateArgs<float> a,
     for (int u = 0; u < CPT; ++u) {
       const int e = threadIdx.x + 512 * u;
       if (e < FR) {
-        short h, l;
-        bf16_split(cv[u], h, l);
+        short h, m, l;
+        bf16_split3(cv[u], h, m, l);
         cf[buf][0][e] = h;
-        cf[buf][1][e] = l;
+        cf[buf][1][e] = m;
+        cf[buf][2][e] = l;
       }
     }
   };
@@ -614,19 +619,23 @@ __global__ __launch_bounds__(512) void update_bf16x3(UpdateArgs<float> a,
     }
 #pragma unroll
     for (int g = 0; g < RG; ++g) {
-      short ah[KPL], al[KPL];
+      short ah[KPL], am[KPL], al[KPL];
 #pragma unroll
-      for (int e = 0; e < KPL; ++e) bf16_split(xc[g][e >> 2][e & 3], ah[e], al[e]);
+      for (int e = 0; e < KPL; ++e) bf16_split3(xc[g][e >> 2][e & 3], ah[e], am[e], al[e]);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        short bh[KPL], bl[KPL];
+        short bh[KPL], bm[KPL], bl[KPL];
 #pragma unroll
         for (int e = 0; e < KPL; ++e) {
           bh[e] = cf[buf][0][(t * 64 + lane) * KPL + e];
-          bl[e] = cf[buf][1][(t * 64 + lane) * KPL + e];
+          bm[e] = cf[buf][1][(t * 64 + lane) * KPL + e];
+          bl[e] = cf[buf][2][(t * 64 + lane) * KPL + e];
         }
         acc[g][t] = mfma_bf16<KPL>(al, bh, acc[g][t]);
         acc[g][t] = mfma_bf16<KPL>(ah, bl, acc[g][t]);
+        acc[g][t] = mfma_bf16<KPL>(am, bm, acc[g][t]);
+        acc[g][t] = mfma_bf16<KPL>(am, bh, acc[g][t]);
+        acc[g][t] = mfma_bf16<KPL>(ah, bm, acc[g][t]);
         acc[g][t] = mfma_bf16<KPL>(ah, bh, acc[g][t]);
       }
     }

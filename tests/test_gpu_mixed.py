@@ -100,3 +100,28 @@ def test_mixed_kappa_1e6_graph_laplacian():
     assert r <= tol
     kappa = 13.13 / 1e-5
     assert g.err_vs_ref <= kappa * (r + 1e-12)
+
+
+@pytest.mark.parametrize("s", [16, 32])
+def test_mixed_wide_blocks_keep_fp32_accuracy(s):
+    """s = 16 and 32 take the FP32 Gram and update on the BF16 matrix cores
+    with three-part splits.  Their products must keep FP32 accuracy: the
+    inner solves' loss of orthogonality stays at the FP32 level (a product
+    at bfloat16 accuracy, 2^-8, would leave it near 1e-2), and the refined
+    solve needs about as many block iterations as the FP64 solve to the
+    same tolerance.  3-D Laplacian 16^3, BGMRES(20) with BCGSI+LS."""
+    A = w.laplace_3d(16)
+    B = w.rhs(A.n, s, seed=21)
+    tol = 1e-8
+    g = gpu_solve(A, B, method="gmres", skeleton="bcgsi_ls", m=20, tol=tol, max_cycles=200,
+                  precision="mixed", max_refine=20, inner_tol=1e-4, record_loo=True)
+    g64 = gpu_solve(A, B, method="gmres", skeleton="bcgsi_ls", m=20, tol=tol, max_cycles=200)
+    r = true_relres(A, g.X, B)
+    loo = np.asarray(g.loo_hist)
+    loo = loo[np.isfinite(loo)]
+    print(f"mixed s={s}: refinement steps {g.refine_steps}, inner block iterations {g.iters}, "
+          f"FP64 iterations {g64.iters}, true relres {r:.2e}, max LOO {loo.max():.2e}")
+    assert g.status == "ok" and g64.status == "ok"
+    assert r <= tol
+    assert loo.size > 0 and loo.max() <= 1e-3
+    assert g.iters <= 1.5 * g64.iters + 10
