@@ -298,28 +298,31 @@ __global__ __launch_bounds__(512) void gram_mfma_wide(GramArgs<T> a, int nchunk,
   const int nchk = kWTR * cpr;
   typedef T wv __attribute__((ext_vector_type(EPC)));
   wv rreg[RPT];
+  // Every thread issues the same loads at every stage, none of them under a
+  // branch (chunks past the stage and rows past r1 read a valid element; the
+  // rows are zeroed only when stored), so the compiler's waits on them are
+  // exact counts and the loads of the stage after next stay in flight
+  // through this stage.
   auto rload = [&](int st) {
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
-      const int e = threadIdx.x + blockDim.x * u;
-      if (e < nchk) {
-        const int row = e / cpr, col = EPC * (e % cpr);
-        const int64_t grow = r0 + (int64_t)st * kWTR + row;
-        const bool ok = grow < r1;
-        const wv v = *reinterpret_cast<const wv*>(a.xr[col / s] + (col % s) +
-                                                  (ok ? grow : r1 - 1) * s);
-        rreg[u] = ok ? v : wv(T(0));   // rows past r1 contribute 0
-      }
+      const int e0 = threadIdx.x + blockDim.x * u;
+      const int e = e0 < nchk ? e0 : nchk - 1;
+      const int row = e / cpr, col = EPC * (e % cpr);
+      const int64_t grow = r0 + (int64_t)st * kWTR + row;
+      rreg[u] = *reinterpret_cast<const wv*>(a.xr[col / s] + (col % s) +
+                                             (grow < r1 ? grow : r1 - 1) * s);
     }
   };
-  auto rstore = [&](int buf) {
+  auto rstore = [&](int buf, int st) {
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       const int e = threadIdx.x + blockDim.x * u;
       if (e < nchk) {
+        const bool ok = r0 + (int64_t)st * kWTR + e / cpr < r1;   // rows past r1 contribute 0
         double* dst = &rs[buf][(e / cpr) * kWLD + EPC * (e % cpr)];
 #pragma unroll
-        for (int q = 0; q < EPC; ++q) dst[q] = (double)rreg[u][q];
+        for (int q = 0; q < EPC; ++q) dst[q] = ok ? (double)rreg[u][q] : 0.0;
       }
     }
   };
@@ -329,17 +332,19 @@ __global__ __launch_bounds__(512) void gram_mfma_wide(GramArgs<T> a, int nchunk,
     const int64_t row = r0 + (int64_t)st * kWTR + 4 * kq + lk;
     const int64_t off = (row < r1 ? row : r1 - 1) * s;
 #pragma unroll
-    for (int i = 0; i < SW; ++i)
-      if (i < nsw) av[kq][i] = (double)Lp[i][off];
+    for (int i = 0; i < SW; ++i) av[kq][i] = (double)Lp[i][off];   // (Lp[i >= nsw]: a valid strip)
   };
-  gd4 acc[SW][NTR];
+  // each 16 x 16 x 4 product as four 4x4x4 products (Mfma4)
+  double acc[SW][NTR][4];
 #pragma unroll
   for (int i = 0; i < SW; ++i)
 #pragma unroll
-    for (int j = 0; j < NTR; ++j) acc[i][j] = gd4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NTR; ++j)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[i][j][t] = 0.0;
   if (nst > 0) {
     rload(0);
-    rstore(0);
+    rstore(0, 0);
     if (nst > 1) rload(1);
 #pragma unroll
     for (int kq = 0; kq < 4; ++kq) lload(0, kq);
@@ -350,32 +355,31 @@ __global__ __launch_bounds__(512) void gram_mfma_wide(GramArgs<T> a, int nchunk,
     const bool more = st + 1 < nst;
 #pragma unroll
     for (int kq = 0; kq < 4; ++kq) {
-      double bv[NTR];
 #pragma unroll
-      for (int j = 0; j < NTR; ++j) bv[j] = R[(4 * kq + lk) * kWLD + 16 * j + lr];
+      for (int j = 0; j < NTR; ++j) {
+        const Mfma4 m(R[(4 * kq + lk) * kWLD + 16 * j + lr]);
 #pragma unroll
-      for (int i = 0; i < SW; ++i)
-        if (i < nsw)
-#pragma unroll
-          for (int j = 0; j < NTR; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kq][i], bv[j], acc[i][j], 0, 0, 0);
-      if (more) lload(st + 1, kq);
+        for (int i = 0; i < SW; ++i)
+          if (i < nsw) m.mac(av[kq][i], acc[i][j]);
+      }
+      lload(more ? st + 1 : st, kq);   // unconditional: its waits stay exact
     }
-    if (more) {
-      rstore((st + 1) & 1);
-      if (st + 2 < nst) rload(st + 2);
-    }
+    if (more) rstore((st + 1) & 1, st + 1);
+    rload(st + 2 < nst ? st + 2 : nst - 1);
     __syncthreads();
   }
+  // lane l = 16 i + 4 g + j: acc[.][.][t] = G[4 g + i][4 ((g - t) mod 4) + j]
   double* out = partial + (int64_t)chunk * PA * QB;
+  const int g = lr >> 2, jj = lr & 3;
 #pragma unroll
   for (int i = 0; i < SW; ++i)
     if (i < nsw)
 #pragma unroll
       for (int j = 0; j < NTR; ++j)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          out[(int64_t)((st0 + i) * 16 + 4 * q + lk) * QB + j * 16 + lr] = acc[i][j][q];
+        for (int t = 0; t < 4; ++t)
+          out[(int64_t)((st0 + i) * 16 + 4 * g + lk) * QB + j * 16 + 4 * ((g - t) & 3) + jj] =
+              acc[i][j][t];
 }
 
 // FP32 Gram for s = 16, 32 on the BF16 matrix cores with FP32 accumulation
@@ -650,9 +654,10 @@ WPlan wplan(int64_t n, int PA, int QB) {
   WPlan p;
   p.ntr = QB / 16;
   const int ns = PA / 16;
-  // above 16 strips: 8 wavefronts per 40 (NTR = 4, at most 5 each) or per
-  // 48 strips (at most 6 each)
-  const int big = p.ntr == 4 ? 5 : 6;
+  // above 16 strips: 8 wavefronts per 32 (NTR = 4, at most 4 each) or per
+  // 48 strips (at most 6 each); more strips per wavefront at NTR = 4 would
+  // leave too few registers for the fragments in flight
+  const int big = p.ntr == 4 ? 4 : 6;
   const int nw = ns <= 4 ? ns : (ns <= 16 ? 4 * ((ns + 15) / 16) : 8 * ((ns + 8 * big - 1) / (8 * big)));
   p.sw = ns <= 16 ? 4 : big;
   p.wpg = nw % 8 == 0 ? 8 : (nw % 4 == 0 ? 4 : nw);
@@ -793,18 +798,35 @@ void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* 
       const int nchunk_pad = ((q.nchunk + kXcds - 1) / kXcds) * kXcds;
       const dim3 g(nchunk_pad * q.ngroup), b(64 * q.wpg);
       const double bytes = (double)distinct_blocks(a) * a.n * a.s * sizeof(T);
-#define LSBA_WIDE(SW, NTR)                                                                   \
-  launch_kf(tm, KK_GRAM, bytes, gflops, gram_mfma_wide<T, SW, NTR, (SW > 4 ? 1 : 8)>, g, b, 0,       \
-           st, a, q.nchunk, q.ngroup, q.wpg, q.rows, partial, ctl)
+      // RPT: 16-byte right-row chunks per thread and stage (every one is
+      // loaded, so it is sized to the workgroup: 16 rows x QB / EPC chunks)
+      const int epc = 16 / (int)sizeof(T);
+      const int per = (16 * (QB / epc) + 64 * q.wpg - 1) / (64 * q.wpg);
+      const int rpt = per <= 1 ? 1 : per <= 2 ? 2 : per <= 4 ? 4 : 8;
+#define LSBA_WIDE(SW, NTR, RPT)                                                              \
+  launch_kf(tm, KK_GRAM, bytes, gflops, gram_mfma_wide<T, SW, NTR, RPT>, g, b, 0, st, a, q.nchunk, \
+            q.ngroup, q.wpg, q.rows, partial, ctl)
+#define LSBA_WIDE_R(SW, NTR)                                                                 \
+  do {                                                                                       \
+    if constexpr (sizeof(T) == sizeof(double)) {                                             \
+      if (rpt == 1) LSBA_WIDE(SW, NTR, 1);                                                   \
+      else if (rpt == 2) LSBA_WIDE(SW, NTR, 2);                                              \
+      else if (rpt == 4) LSBA_WIDE(SW, NTR, 4);                                              \
+      else LSBA_WIDE(SW, NTR, 8);                                                            \
+    } else {                                                                                 \
+      if (rpt == 1) LSBA_WIDE(SW, NTR, 1);                                                   \
+      else LSBA_WIDE(SW, NTR, 8);                                                            \
+    }                                                                                        \
+  } while (0)
       if (q.sw == 4) {
-        if (q.ntr == 4) LSBA_WIDE(4, 4);
-        else if (q.ntr == 2) LSBA_WIDE(4, 2);
-        else LSBA_WIDE(4, 1);
+        if (q.ntr == 4) LSBA_WIDE_R(4, 4);
+        else if (q.ntr == 2) LSBA_WIDE_R(4, 2);
+        else LSBA_WIDE_R(4, 1);
       } else {
-        if (q.ntr == 4) LSBA_WIDE(5, 4);
-        else if (q.ntr == 2) LSBA_WIDE(6, 2);
-        else LSBA_WIDE(6, 1);
+        if (q.ntr == 2) LSBA_WIDE(6, 2, 1);
+        else LSBA_WIDE(6, 1, 1);
       }
+#undef LSBA_WIDE_R
 #undef LSBA_WIDE
       launch_stage2(st, partial, q.nchunk, PA * QB, out, ctl, tm);
       return;

@@ -284,9 +284,13 @@ __global__ __launch_bounds__(256) void update_mfma8(UpdateArgs<double> a, const 
 // of step h holds coefficient row c(h, l / 16).  The next input's rows and
 // coefficients are loaded while the current one is multiplied.  Every
 // output row depends on its own input rows only, so rows past n read a
-// valid row and are not written.  (The 4x4x4 FP64 instruction issues at
-// twice the rate on gfx950 but needs the row operand replicated in four
-// lanes; measured here, that version of this kernel was 1.75x slower.)
+// valid row and are not written.  Each 16 x 16 x 4 product is issued as
+// four v_mfma_f64_4x4x4f64 with the coefficient fragment rotated across the
+// lane groups (Mfma4), twice the FP64 matrix rate of the 16x16x4 form on
+// gfx950.  Every global load is unconditional (missing coefficient blocks
+// read a valid word and are zeroed when staged), so the compiler's waits on
+// them are exact counts and the next input's loads stay in flight through
+// the current input's products.
 constexpr int kWideRG = 2;
 
 __device__ __forceinline__ int wide_kcol(int h, int q) { return 2 * q + (h & 1) + 8 * (h >> 1); }
@@ -336,38 +340,36 @@ __global__ __launch_bounds__(512) void update_mfma_wide(UpdateArgs<double> a,
   }
   // coefficient fragment entries this thread stages: e = threadIdx.x + 512 u
   constexpr int CPT = (FR + 511) / 512;
-  auto coef_load = [&](int q, double (&cv)[CPT]) {
+  auto coef_load = [&](int q, double (&cv)[CPT], bool (&cok)[CPT]) {
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
-      const int e = threadIdx.x + 512 * u;
-      double v = 0.0;
-      if (e < FR) {
-        const int l = e & 63, tq = e >> 6;
-        const int t = tq % NT, h = tq / NT;
-        const int half = t / (NT / 2);
-        const int col = (t % (NT / 2)) * 16 + (l & 15);
-        const int krow = wide_kcol(h, l >> 4);
-        const double* blk = nullptr;
-        if (q < in.h1) {
-          blk = half ? (FOLD ? a.coef + a.lay.C1D() : nullptr) : a.coef + a.lay.C1();
-        } else if (q - in.h1 < in.nbas) {
-          const int i = in.i0 + q - in.h1;
-          if (!half) blk = i < nv1 ? a.coef + a.lay.A(i) : nullptr;
-          else if (FOLD) blk = a.coef + a.lay.BF(i);
-          else blk = (i >= nb && i < nv2) ? a.coef + a.lay.B(i) : nullptr;
-        } else {
-          blk = half ? a.coef + a.lay.C2() : nullptr;
-        }
-        if (blk) v = blk[krow * S + col];
+      const int e0 = threadIdx.x + 512 * u;
+      const int e = e0 < FR ? e0 : FR - 1;
+      const int l = e & 63, tq = e >> 6;
+      const int t = tq % NT, h = tq / NT;
+      const int half = t / (NT / 2);
+      const int col = (t % (NT / 2)) * 16 + (l & 15);
+      const int krow = wide_kcol(h, l >> 4);
+      const double* blk = nullptr;
+      if (q < in.h1) {
+        blk = half ? (FOLD ? a.coef + a.lay.C1D() : nullptr) : a.coef + a.lay.C1();
+      } else if (q - in.h1 < in.nbas) {
+        const int i = in.i0 + q - in.h1;
+        if (!half) blk = i < nv1 ? a.coef + a.lay.A(i) : nullptr;
+        else if (FOLD) blk = a.coef + a.lay.BF(i);
+        else blk = (i >= nb && i < nv2) ? a.coef + a.lay.B(i) : nullptr;
+      } else {
+        blk = half ? a.coef + a.lay.C2() : nullptr;
       }
-      cv[u] = v;
+      cok[u] = blk != nullptr;
+      cv[u] = (blk ? blk : a.coef)[krow * S + col];   // a missing block reads a valid word
     }
   };
-  auto coef_store = [&](int buf, const double (&cv)[CPT]) {
+  auto coef_store = [&](int buf, const double (&cv)[CPT], const bool (&cok)[CPT]) {
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
       const int e = threadIdx.x + 512 * u;
-      if (e < FR) cf[buf][e] = cv[u];
+      if (e < FR) cf[buf][e] = cok[u] ? cv[u] : 0.0;
     }
   };
   typedef double dbl2 __attribute__((ext_vector_type(2)));
@@ -379,26 +381,30 @@ __global__ __launch_bounds__(512) void update_mfma_wide(UpdateArgs<double> a,
       for (int j = 0; j < NCH; ++j)
         x[g][j] = *reinterpret_cast<const dbl2*>(p + roff[g] + 8 * j);
   };
-  ud4 acc[RG][NT];
+  double acc[RG][NT][4];
 #pragma unroll
   for (int g = 0; g < RG; ++g)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[g][t] = ud4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[g][t][r] = 0.0;
   dbl2 xc[RG][NCH], xn[RG][NCH];
   double cvn[CPT];
+  bool cok[CPT];
   if (nin > 0) {
-    coef_load(0, cvn);
+    coef_load(0, cvn, cok);
     rows_load(0, xc);
-    coef_store(0, cvn);
+    coef_store(0, cvn, cok);
   }
   __syncthreads();
   for (int q = 0; q < nin; ++q) {
     const int buf = q & 1;
     const bool more = q + 1 < nin;
-    if (more) {
-      coef_load(q + 1, cvn);
-      rows_load(q + 1, xn);
-    }
+    const int qn = more ? q + 1 : q;   // loads are unconditional (exact waits)
+    coef_load(qn, cvn, cok);
+    rows_load(qn, xn);
+    // the row fragments (RG per K-step) are the rotated operands: fewer
+    // than the coefficient fragments (NT per K-step)
 #pragma unroll
     for (int h = 0; h < KS; ++h) {
       double bf[NT];
@@ -406,32 +412,31 @@ __global__ __launch_bounds__(512) void update_mfma_wide(UpdateArgs<double> a,
       for (int t = 0; t < NT; ++t) bf[t] = cf[buf][(h * NT + t) * 64 + lane];
 #pragma unroll
       for (int g = 0; g < RG; ++g) {
-        const double av = (h & 1) ? xc[g][h >> 1].y : xc[g][h >> 1].x;
+        const Mfma4 m((h & 1) ? xc[g][h >> 1].y : xc[g][h >> 1].x);
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-          acc[g][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bf[t], acc[g][t], 0, 0, 0);
+        for (int t = 0; t < NT; ++t) m.mac_a(bf[t], acc[g][t]);
       }
     }
-    if (more) {
-      coef_store(buf ^ 1, cvn);
+    if (more) coef_store(buf ^ 1, cvn, cok);
 #pragma unroll
-      for (int g = 0; g < RG; ++g)
+    for (int g = 0; g < RG; ++g)
 #pragma unroll
-        for (int j = 0; j < NCH; ++j) xc[g][j] = xn[g][j];
-    }
+      for (int j = 0; j < NCH; ++j) xc[g][j] = xn[g][j];
     __syncthreads();
   }
+  // lane l = 16 i + 4 b + j: acc[g][t][r] = out[row 4 ((b - r) mod 4) + i][tile col 4 b + j]
   const bool w2 = a.out2 && (a.in2 || nv2 > nb);
+  const int bq = lr >> 2, jq = lr & 3;
 #pragma unroll
-  for (int g = 0; g < RG; ++g)
+  for (int g = 0; g < RG; ++g) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t row = wrow0 + 16 * g + 4 * r + lq;
+      const int64_t row = wrow0 + 16 * g + 4 * ((bq - r) & 3) + lq;
       if (row >= a.n) continue;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int half = t / (NT / 2);
-        const int col = (t % (NT / 2)) * 16 + lr;
+        const int col = (t % (NT / 2)) * 16 + 4 * bq + jq;
         if (!half) {
           if (a.out1) a.out1[row * S + col] = acc[g][t][r];
         } else if (w2) {
@@ -439,6 +444,7 @@ __global__ __launch_bounds__(512) void update_mfma_wide(UpdateArgs<double> a,
         }
       }
     }
+  }
 }
 
 // FP32 blocks, s = 16 or 32, on the BF16 matrix cores with FP32

@@ -247,4 +247,44 @@ template <typename T>
 void launch_house(hipStream_t st, const Dense& d, int64_t n, int s, const T* X, T* out1, T* out2,
                   double* work, int mode, int k, int force, KTimer* tm = nullptr);
 
+// v rotated right by N lanes within each row of 16 lanes (DPP row_ror):
+// lane 16 r + i receives the value of lane 16 r + ((i - N) mod 16).
+template <int N>
+__device__ __forceinline__ double row_ror(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, 0x120 + N, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x120 + N, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned long long)(unsigned)lo));
+}
+
+// The FP64 16 x 16 x 4 product acc[t] += A B as four v_mfma_f64_4x4x4f64
+// (twice the issue rate of v_mfma_f64_16x16x4f64 on gfx950).  a and b hold
+// the 16x16x4 operands (lane l: A[l % 16][l / 16], B[l / 16][l % 16]); the
+// 4x4x4 instruction multiplies, for each of the four lane groups g = (l % 16)
+// / 4, the 4 x 4 blocks A[4 g .. 4 g + 3][:] and B[:][4 g' .. 4 g' + 3] with
+// g' = g, so b rotated by 4 t lanes pairs group g with g' = (g - t) mod 4.
+// acc[t] at lane l = 16 i + 4 g + j holds D[4 g + i][4 ((g - t) mod 4) + j]
+// (mac), or with the rotated operand taken as A, D[4 ((g - t) mod 4) + i][4 g + j]
+// (mac_a).
+struct Mfma4 {
+  double b[4];
+  __device__ __forceinline__ explicit Mfma4(double bv) {
+    b[0] = bv;
+    b[1] = row_ror<4>(bv);
+    b[2] = row_ror<8>(bv);
+    b[3] = row_ror<12>(bv);
+  }
+  __device__ __forceinline__ void mac(double a, double (&acc)[4]) const {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b[t], acc[t], 0, 0, 0);
+  }
+  // the same product with the stored operand rotated in the A position:
+  // acc[t] at lane l = 16 i + 4 g + j holds D[4 ((g - t) mod 4) + i][4 g + j]
+  __device__ __forceinline__ void mac_a(double bv, double (&acc)[4]) const {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(b[t], bv, acc[t], 0, 0, 0);
+  }
+};
+
 }  // namespace lsba
