@@ -71,7 +71,9 @@ typedef enum {
   LSBA_BMGS_SVL = 1,          /* Alg. 5, Schreiber-Van Loan T update */
   LSBA_BMGS_LTS = 2,          /* Alg. 5, lower-triangular-solve T update */
   LSBA_BMGS_CWY = 3,          /* Alg. 6, compact WY */
-  LSBA_BMGS_ICWY = 4          /* Alg. 6, inverse compact WY */
+  LSBA_BMGS_ICWY = 4,         /* Alg. 6, inverse compact WY */
+  LSBA_BCGS_PIP = 5,          /* Alg. 3, one fused inner product + Pythagorean Cholesky */
+  LSBA_BMGS = 6               /* Alg. 2, the block MGS baseline: k + 1 syncs at step k */
 } lsba_skeleton;
 
 typedef enum { LSBA_CHOLQR = 0, LSBA_HOUSEQR = 1 } lsba_muscle;

@@ -261,7 +261,7 @@ __global__ __launch_bounds__(HT) void house_top_kernel(const T* in, int64_t nrow
   const int ss = s * s;
   const bool ok = okf != 0;
   if (mode == HM_START) {
-    if (d.skel != LSBA_BCGSI_LS)
+    if (skel_uses_t(d.skel))
       for (int64_t e = threadIdx.x; e < (int64_t)d.ldh * d.ldh; e += HT) {
         const double v = ((e / d.ldh) == (e % d.ldh)) ? 1.0 : 0.0;
         d.T[e] = v;

@@ -1051,6 +1051,80 @@ __global__ __launch_bounds__(NT) void small_svl_z_kernel(Dense d, int k) {
   }
 }
 
+// Alg. 3 (BCGS-PIP), loop step k (1-based).  From the one fused Gram
+// [Y; Omega] = [V_{1:k} W]^T W: H_{1:k,k} = Y, H_{k+1,k} = R = chol(Omega -
+// Y^T Y) (the Pythagorean form of the norm of W - V_{1:k} Y, with the
+// breakdown flag of Sec. 4), and the coefficients of the one projection
+// V_{k+1} = (W - V_{1:k} Y) R^{-1} (C2 = R^{-1}, B_i = -Y_i R^{-1}).
+// Column k of H is final afterwards.  FIT: the Gram output is copied to LDS.
+template <bool FIT>
+__global__ __launch_bounds__(NT) void small_pip_kernel(Dense d, int k, int force) {
+  __shared__ double lds[LDS_DBL];
+  Ctl* ctl = d.ctl;
+  if (ctl->stop) return;
+  const int s = d.s, ld = d.ldh, ss = s * s, ks = k * s;
+  CoefLayout lay{s, d.mmax + 1};
+  double* Om = lds;
+  double* R = Om + ss;
+  double* Ri = R + ss;
+  double* dinv = Ri + ss;   // kMaxS
+  const int lused = 3 * ss + kMaxS;
+  const double* Gp;
+  if constexpr (FIT) {
+    bcopy(d.G, lds + lused, (ks + s) * s);
+    Gp = lds + lused;
+    bar();
+  } else {
+    Gp = d.G;
+  }
+  // Omega - Y^T Y
+  mm_t<true, false>(s, s, ks, -1.0, Gp, s, Gp, s, 0.0, Om, s, Gp + (int64_t)ks * s, s);
+  bool ok = chol_flag(d, Om, s, R, dinv);
+  if (force) ok = false;
+  if (!ok) {
+    if (threadIdx.x == 0) raise_flag(ctl, k, k - 1);
+    return;
+  }
+  tri_inv_up(R, s, Ri, dinv);
+  double* coef = d.coef64;
+  double* Hc = d.H + (int64_t)(k - 1) * s;
+  for (int e = threadIdx.x; e < ss; e += NT) {
+    coef[lay.C2() + e] = Ri[e];
+    d.Rinv[e] = Ri[e];
+    Hc[(int64_t)(ks + e / s) * ld + (e % s)] = R[e];
+  }
+  // one pass over the rows of Y: H_{1:k,k} = Y and B = -Y R^{-1}
+  for (int e = threadIdx.x; e < ks * s; e += NT) {
+    const int i = e / s, c = e % s;
+    const double* y = Gp + (int64_t)i * s;
+    double b = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < s; ++t) b = fma(y[t], Ri[t * s + c], b);
+    coef[lay.B(0) + e] = -b;
+    Hc[(int64_t)i * ld + c] = y[c];
+  }
+  bar();
+  publish_coef(d);
+}
+
+// Alg. 2 (BMGS), loop step k, inner step i (both 1-based): H_{i,k} = V_i^T W
+// (the Gram output) and the coefficients of W <- W - V_i H_{i,k}.
+__global__ __launch_bounds__(NT) void small_bmgs_kernel(Dense d, int k, int i) {
+  Ctl* ctl = d.ctl;
+  if (ctl->stop) return;
+  const int s = d.s, ld = d.ldh, ss = s * s;
+  CoefLayout lay{s, d.mmax + 1};
+  double* Hc = d.H + (int64_t)(i - 1) * s * ld + (k - 1) * s;
+  for (int e = threadIdx.x; e < ss; e += NT) {
+    const double v = d.G[e];
+    Hc[(int64_t)(e / s) * ld + (e % s)] = v;
+    d.coef64[lay.C2() + e] = (e / s == e % s) ? 1.0 : 0.0;
+    d.coef64[lay.B(i - 1) + e] = -v;
+  }
+  bar();
+  publish_coef(d);
+}
+
 }  // namespace
 
 #define SMALL_LAUNCH(...)                 \
@@ -1061,7 +1135,7 @@ __global__ __launch_bounds__(NT) void small_svl_z_kernel(Dense d, int k) {
   } while (0)
 
 void launch_small_start(hipStream_t st, const Dense& d, int force_flag, KTimer* tm) {
-  if (d.skel != LSBA_BCGSI_LS) {
+  if (skel_uses_t(d.skel)) {
     const int64_t tot = (int64_t)d.ldh * d.ldh;
     const int blocks = (int)std::min<int64_t>((tot + NT - 1) / NT, 1024);
     SMALL_LAUNCH(t_identity_kernel<<<blocks, NT, 0, st>>>(d));
@@ -1103,5 +1177,15 @@ void launch_small_svl_io(hipStream_t st, const Dense& d, int k, int force_flag, 
 }
 void launch_small_svl_z(hipStream_t st, const Dense& d, int k, KTimer* tm) {
   SMALL_LAUNCH(small_svl_z_kernel<<<1, NT, 0, st>>>(d, k));
+}
+void launch_small_pip(hipStream_t st, const Dense& d, int k, int force_flag, KTimer* tm) {
+  const int s = d.s;
+  if ((k + 1) * s * s <= LDS_DBL - (3 * s * s + kMaxS))
+    SMALL_LAUNCH(small_pip_kernel<true><<<1, NT, 0, st>>>(d, k, force_flag));
+  else
+    SMALL_LAUNCH(small_pip_kernel<false><<<1, NT, 0, st>>>(d, k, force_flag));
+}
+void launch_small_bmgs(hipStream_t st, const Dense& d, int k, int i, KTimer* tm) {
+  SMALL_LAUNCH(small_bmgs_kernel<<<1, NT, 0, st>>>(d, k, i));
 }
 }  // namespace lsba

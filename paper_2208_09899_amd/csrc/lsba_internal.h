@@ -233,6 +233,18 @@ void launch_small_svl_y(hipStream_t st, const Dense& d, int k, KTimer* tm = null
 void launch_small_svl_io(hipStream_t st, const Dense& d, int k, int force_flag,
                          KTimer* tm = nullptr);
 void launch_small_svl_z(hipStream_t st, const Dense& d, int k, KTimer* tm = nullptr);
+// Alg. 3 (BCGS-PIP), loop step k: H_{1:k,k}, H_{k+1,k} (flag) and the
+// projection coefficients from [V_{1:k} W]^T W.
+void launch_small_pip(hipStream_t st, const Dense& d, int k, int force_flag,
+                      KTimer* tm = nullptr);
+// Alg. 2 (BMGS), loop step k, inner step i: H_{i,k} = V_i^T W and the
+// coefficients of W <- W - V_i H_{i,k}.
+void launch_small_bmgs(hipStream_t st, const Dense& d, int k, int i, KTimer* tm = nullptr);
+// skeletons that keep the T factor (Algs. 5, 6)
+__host__ __device__ inline bool skel_uses_t(int sk) {
+  return sk == LSBA_BMGS_SVL || sk == LSBA_BMGS_LTS || sk == LSBA_BMGS_CWY ||
+         sk == LSBA_BMGS_ICWY;
+}
 void launch_small_cycle_end(hipStream_t st, const Dense& d, KTimer* tm = nullptr);
 void launch_small_loo(hipStream_t st, const Dense& d, int k_new_block, KTimer* tm = nullptr);
 

@@ -208,8 +208,10 @@ struct EventTimer final : KTimer {
 
 // Counts of one cycle as the paper counts them (Sec. 5): A-calls, basis
 // applications and syncs of the loop steps the algorithm executed.
-void cycle_counts(bool delayed, bool bcgs, int j, int status, int flag_step, int64_t& a,
-                  int64_t& v, int64_t& sy) {
+void cycle_counts(int skel, int j, int status, int flag_step, int64_t& a, int64_t& v,
+                  int64_t& sy) {
+  const bool delayed = skel == LSBA_BCGSI_LS || skel == LSBA_BMGS_CWY || skel == LSBA_BMGS_ICWY;
+  const bool bcgs = skel == LSBA_BCGSI_LS;
   sy += 1;   // IntraOrtho of the starting block
   if (status == ST_FLAGGED && flag_step == 0) return;
   int full, partial = 0;
@@ -218,6 +220,23 @@ void cycle_counts(bool delayed, bool bcgs, int j, int status, int flag_step, int
     partial = 1;
   } else {
     full = delayed ? j + 1 : j;
+  }
+  if (skel == LSBA_BCGS_PIP) {
+    // step k: one A-call, one fused inner product (2 applications of the
+    // basis), one projection; a flagged step stops before the projection
+    a += full + partial;
+    sy += full + partial;
+    v += 3 * full + 2 * partial;
+    return;
+  }
+  if (skel == LSBA_BMGS) {
+    // step k: one A-call, k block inner products and the IntraOrtho
+    for (int k = 1; k <= full + partial; ++k) {
+      a += 1;
+      sy += k + 1;
+      v += 2;
+    }
+    return;
   }
   if (delayed) {
     for (int k = 1; k <= full; ++k) {
@@ -767,6 +786,67 @@ struct CycleRunner {
           launch_small_loo(st, d, kk, tm);
         }
       }
+    } else if (p.skeleton == LSBA_BCGS_PIP) {
+      // Alg. 3: SpMM, one fused inner product [V_{1:k} W]^T W, the
+      // Pythagorean Cholesky (H column final), one projection
+      for (int kk = 1; kk <= m; ++kk) {
+        const int force = fk == kk ? 1 : 0;
+        tag(kk, 0);
+        launch_spmm<T>(st, n, op->nnz, s, op->rp, op->ci, val, slot(k, kk - 1), k.W, ctl, tm);
+        launch_gram<T>(st, gram_args<T>(k, kk, {k.W}, {k.W}), k.partial, d.G, ctl, tm);
+        launch_small_pip(st, d, kk, force, tm);
+        tag(kk, 1);
+        finalize_after(kk, kk);
+        UpdateArgs<T> u = upd_args(k);
+        u.in2 = k.W;
+        u.out2 = slot(k, kk);
+        u.nv2_begin = 0;
+        u.nv2 = kk;
+        launch_update<T>(st, u, ctl, true, tm);
+        if (rec_loo) {
+          launch_gram<T>(st, gram_args<T>(k, kk + 1, {}, {slot(k, kk)}), k.partial, d.G2, ctl,
+                         tm);
+          launch_small_loo(st, d, kk + 1, tm);
+        }
+      }
+    } else if (p.skeleton == LSBA_BMGS) {
+      // Alg. 2: SpMM, then for i = 1..k one inner product V_i^T W and one
+      // subtraction each (in place on W), then the IntraOrtho of W
+      for (int kk = 1; kk <= m; ++kk) {
+        const int force = fk == kk ? 1 : 0;
+        tag(kk, 0);
+        launch_spmm<T>(st, n, op->nnz, s, op->rp, op->ci, val, slot(k, kk - 1), k.W, ctl, tm);
+        for (int i = 1; i <= kk; ++i) {
+          launch_gram<T>(st, gram_args<T>(k, 0, {slot(k, i - 1)}, {k.W}), k.partial, d.G, ctl,
+                         tm);
+          launch_small_bmgs(st, d, kk, i, tm);
+          UpdateArgs<T> u = upd_args(k);
+          u.in2 = k.W;
+          u.out2 = k.W;
+          u.nv2_begin = i - 1;
+          u.nv2 = i;
+          launch_update<T>(st, u, ctl, true, tm);
+        }
+        if (p.muscle == LSBA_HOUSEQR) {
+          launch_house<T>(st, d, n, s, k.W, slot(k, kk), (T*)nullptr, k.hwork, HM_IO, kk, force,
+                          tm);
+          tag(kk, 1);
+        } else {
+          launch_gram<T>(st, gram_args<T>(k, 0, {k.W}, {k.W}), k.partial, d.G2, ctl, tm);
+          launch_small_svl_io(st, d, kk, force, tm);
+          tag(kk, 1);
+          UpdateArgs<T> u = upd_args(k);
+          u.in1 = k.W;
+          u.out1 = slot(k, kk);
+          launch_update<T>(st, u, ctl, true, tm);
+        }
+        finalize_after(kk, kk);
+        if (rec_loo) {
+          launch_gram<T>(st, gram_args<T>(k, kk + 1, {}, {slot(k, kk)}), k.partial, d.G2, ctl,
+                         tm);
+          launch_small_loo(st, d, kk + 1, tm);
+        }
+      }
     } else {
       for (int kk = 1; kk <= m; ++kk) {
         const int force = fk == kk ? 1 : 0;
@@ -856,7 +936,7 @@ struct CycleRunner {
         tm->kill_after(hc.flag_step, true);
       tm->flush();
     }
-    cycle_counts(delayed, bcgs, j, cst, hc.flag_step, out.a, out.v, out.sy);
+    cycle_counts(p.skeleton, j, cst, hc.flag_step, out.a, out.v, out.sy);
     for (int i = 0; i < j; ++i) res->res.push_back(c->hist_host[i]);
     if (rec_loo) {
       for (int i = 0; i < j; ++i) {
@@ -1013,7 +1093,7 @@ void validate_params(const lsba_params* p, int s) {
   if (s < 1 || s > kMaxS) throw ArgError{"s must be in [1, 32]"};
   if (p->m < 1 || p->m > kMaxM) throw ArgError{"m must be in [1, 128]"};
   if (p->method != LSBA_FOM && p->method != LSBA_GMRES) throw ArgError{"bad method"};
-  if (p->skeleton < LSBA_BCGSI_LS || p->skeleton > LSBA_BMGS_ICWY) throw ArgError{"bad skeleton"};
+  if (p->skeleton < LSBA_BCGSI_LS || p->skeleton > LSBA_BMGS) throw ArgError{"bad skeleton"};
   if (p->muscle != LSBA_CHOLQR && p->muscle != LSBA_HOUSEQR) throw ArgError{"bad muscle"};
   if (p->precision != LSBA_FP64 && p->precision != LSBA_MIXED) throw ArgError{"bad precision"};
   if (!(p->tol >= 0.0)) throw ArgError{"tol must be >= 0"};

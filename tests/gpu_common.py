@@ -34,6 +34,15 @@ def oracle_solve(csr, B, method="gmres", skeleton="bcgsi_ls", m=20, tol=1e-8, ma
 STATUS_MAP = {"ok": "ok", "not_converged": "not_converged", "breakdown": "breakdown"}
 
 
+def pip_hist_atol(kappa):
+    """History floor for BCGS-PIP (Alg. 3): it forms the norm of the projected
+    block as chol(Omega - Y^T Y), whose rounding error relative to
+    ||W - V Y||^2 is u ||W||^2 / ||W - V Y||^2, so its basis and estimates
+    move by O(u kappa(A)^2) between two FP64 evaluation orders rather than
+    O(u kappa(A)) (the Pythagorean form's known sensitivity, Sec. 3.1)."""
+    return 10 * 1.1e-16 * kappa ** 2
+
+
 def assert_parity(g, o, x_tol=1e-10, hist_rtol=1e-8, hist_atol=1e-12, check_counts=True):
     """The GPU FP64 result matches the oracle: same status, iteration count,
     restart points and counts, X to x_tol (relative, Frobenius), and the
