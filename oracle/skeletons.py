@@ -153,6 +153,51 @@ class BCGS_PIP(_Skeleton):
             yield k
 
 
+class BCGS_PIO(_Skeleton):
+    """BCGS-PIO-Arnoldi, Alg. 4 (Sec. 3.1): the block inner product
+    H_{1:k,k} = V_{1:k}^T W, then the IntraOrtho of the block-diagonal
+    matrix [W 0; 0 H_{1:k,k}] ((n + k s) x 2 s), whose R factor is block
+    diagonal [R_W 0; 0 R_H]; H_{k+1,k} = chol(R_W^T R_W - R_H^T R_H) (the
+    Pythagorean correction from the two triangular factors instead of the
+    Gram blocks) and one projection.  Two syncs per step: the inner product
+    and the IntraOrtho (Table 2: 2m + 1 per cycle).  A flag from the
+    IntraOrtho or from the Cholesky stops the cycle with k - 1 final
+    columns."""
+
+    def run(self, R0):
+        V1, self.Beta, _, ok = self.start(R0)
+        if not ok:
+            self.flagged, self.last = True, 0
+            return
+        self.V = [V1]
+        H, s = self.H, self.s
+        for k in range(1, self.m + 1):
+            W = self.matvec(self.V[k - 1])
+            Vk = self.Vcat(k)
+            self.ct.syncs += 1
+            self.ct.v_apps += 1
+            Hk = ip(Vk, W)
+            H[self.upto(k), self.blk(k)] = Hk
+            n = W.shape[0]
+            D = np.zeros((n + k * s, 2 * s))
+            D[:n, :s] = W
+            D[n:, s:] = Hk
+            self.ct.syncs += 1
+            _, RD, _, ok = intra_ortho(D, self.muscle)
+            if ok:
+                RW, RH = RD[:s, :s], RD[s:, s:]
+                R, ok = self.chol(RW.T @ RW - RH.T @ RH, k)
+            elif k in self.force_steps:
+                ok = False
+            if not ok:
+                self.flagged, self.last = True, k - 1
+                return
+            H[self.blk(k + 1), self.blk(k)] = R
+            self.ct.v_apps += 1
+            self.V.append(right_solve_upper(W - Vk @ Hk, R))
+            yield k
+
+
 class BMGS_SVL(_Skeleton):
     """BMGS-SVL / BMGS-LTS-Arnoldi, Alg. 5 (Sec. 3.2).
 
@@ -334,6 +379,7 @@ class BCGSI_LS(_Skeleton):
 SKELETONS = {
     "bmgs": BMGS,
     "bcgs_pip": BCGS_PIP,
+    "bcgs_pio": BCGS_PIO,
     "bmgs_svl": BMGS_SVL,
     "bmgs_lts": BMGS_LTS,
     "bmgs_cwy": BMGS_CWY,

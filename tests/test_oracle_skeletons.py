@@ -10,7 +10,7 @@ from oracle.skeletons import Counters, make_skeleton
 from paper_2208_09899_amd import workloads as w
 
 STABLE = ["bmgs", "bmgs_svl", "bmgs_lts", "bmgs_cwy", "bmgs_icwy", "bcgsi_ls"]
-ALL = STABLE + ["bcgs_pip"]
+ALL = STABLE + ["bcgs_pip", "bcgs_pio"]
 
 
 def _cycle(name, A, B, m, muscle="cholqr"):
@@ -60,7 +60,7 @@ def test_skeletons_agree_in_exact_arithmetic(name):
     assert j == 8
     # BCGS-PIP's loss of orthogonality grows like eps * kappa^2 of the Krylov
     # basis (Table 2), which here gains about a factor 10 per block column.
-    tol = 1e-6 if name == "bcgs_pip" else 1e-10
+    tol = 1e-6 if name in ("bcgs_pip", "bcgs_pio") else 1e-10
     assert np.linalg.norm(sk.Hm1m(8) - ref.Hm1m(8)) <= tol * np.linalg.norm(ref.Hm1m(8))
     assert np.linalg.norm(sk.Vcat(9) - ref.Vcat(9)) <= tol * 3
 
@@ -76,7 +76,8 @@ def test_hessenberg_spectrum_closed_form(name, n, s, m):
     Hm = sk.H[: m * s, : m * s]
     ev = np.sort(np.linalg.eigvals(Hm).real)
     exact = np.sort(2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
-    tol = 1e-7 if name == "bcgs_pip" else 1e-10     # PIP: O(eps kappa^2) loss of orthogonality
+    # PIP / PIO: O(eps kappa^2) loss of orthogonality (Table 2)
+    tol = 1e-7 if name in ("bcgs_pip", "bcgs_pio") else 1e-10
     assert np.max(np.abs(ev - exact)) <= tol
 
 
@@ -105,6 +106,7 @@ def test_counters_per_cycle(name):
     expect = {
         "bmgs": (j, 2 * j, j * (j + 1) // 2 + j + 1),
         "bcgs_pip": (j, 3 * j, j + 1),
+        "bcgs_pio": (j, 2 * j, 2 * j + 1),
         "bmgs_svl": (j, 3 * j, 3 * j + 1),
         "bmgs_lts": (j, 3 * j, 3 * j + 1),
         "bmgs_cwy": (j + 1, 3 * j + 1, j + 2),
@@ -112,3 +114,40 @@ def test_counters_per_cycle(name):
         "bcgsi_ls": (j + 1, 4 * j + 1, j + 2),
     }[name]
     assert ct.as_tuple() == expect
+
+
+@pytest.mark.parametrize("muscle", ["cholqr", "houseqr"])
+def test_pio_intraortho_of_block_diagonal(muscle):
+    """Alg. 4's IntraOrtho of [W 0; 0 H]: the columns of the two blocks are
+    orthogonal to each other, so R is block diagonal [R_W 0; 0 R_H] with
+    R_W^T R_W = W^T W and R_H^T R_H = H^T H (the QR factors of each block)."""
+    from oracle.primitives import intra_ortho
+    rng = np.random.default_rng(7)
+    n, k, s = 300, 5, 3
+    W = rng.standard_normal((n, s))
+    Hk = rng.standard_normal((k * s, s))
+    D = np.zeros((n + k * s, 2 * s))
+    D[:n, :s] = W
+    D[n:, s:] = Hk
+    Q, R, _, ok = intra_ortho(D, muscle)
+    assert ok
+    assert np.linalg.norm(R[:s, s:]) <= 1e-13 * np.linalg.norm(R)
+    assert np.allclose(R[:s, :s].T @ R[:s, :s], W.T @ W, rtol=1e-12, atol=1e-12 * np.linalg.norm(W) ** 2)
+    assert np.allclose(R[s:, s:].T @ R[s:, s:], Hk.T @ Hk, rtol=1e-12, atol=1e-12 * np.linalg.norm(Hk) ** 2)
+    assert np.linalg.norm(Q @ R - D) <= 1e-13 * np.linalg.norm(D)
+
+
+def test_pio_equals_pip_on_a_well_conditioned_cycle():
+    """Algs. 3 and 4 compute H_{k+1,k} from the same quantity (Omega - H^T H
+    = R_W^T R_W - R_H^T R_H in exact arithmetic), so their bases and
+    Hessenberg matrices agree to rounding over the first columns.  Both have
+    O(eps kappa^2) loss of orthogonality (Table 2) and kappa of the block
+    Krylov basis grows with every column, so the rounding difference grows
+    too: measured here 2e-14, 2e-13, 3e-12, 4e-11 after 2..5 columns; the
+    check is on 3 columns."""
+    A = (w.laplace_2d(20).to_scipy() + 4.0 * sp.identity(400)).tocsr()
+    B = w.rhs(400, 3, 9)
+    pip, _ = _cycle("bcgs_pip", A, B, 3)
+    pio, _ = _cycle("bcgs_pio", A, B, 3)
+    assert np.linalg.norm(pio.Hm1m(3) - pip.Hm1m(3)) <= 1e-11 * np.linalg.norm(pip.Hm1m(3))
+    assert np.linalg.norm(pio.Vcat(4) - pip.Vcat(4)) <= 1e-11
