@@ -73,7 +73,8 @@ typedef enum {
   LSBA_BMGS_CWY = 3,          /* Alg. 6, compact WY */
   LSBA_BMGS_ICWY = 4,         /* Alg. 6, inverse compact WY */
   LSBA_BCGS_PIP = 5,          /* Alg. 3, one fused inner product + Pythagorean Cholesky */
-  LSBA_BMGS = 6               /* Alg. 2, the block MGS baseline: k + 1 syncs at step k */
+  LSBA_BMGS = 6,              /* Alg. 2, the block MGS baseline: k + 1 syncs at step k */
+  LSBA_BCGS_PIO = 7           /* Alg. 4, inner product + IntraOrtho of [W 0; 0 H]: 2 syncs/step */
 } lsba_skeleton;
 
 typedef enum { LSBA_CHOLQR = 0, LSBA_HOUSEQR = 1 } lsba_muscle;

@@ -1107,6 +1107,88 @@ __global__ __launch_bounds__(NT) void small_pip_kernel(Dense d, int k, int force
   publish_coef(d);
 }
 
+// Alg. 4 (BCGS-PIO), loop step k (1-based).  Y = H_{1:k,k} = V_{1:k}^T W is
+// in G; the IntraOrtho of the block-diagonal [W 0; 0 Y] has the R factor
+// [R_W 0; 0 R_H]: with CholQR, R_W = chol(W^T W) (W^T W in G2) and
+// R_H = chol(Y^T Y), each flagging; with HouseQR, R_W is the TSQR factor
+// already in H_{k+1,k} (it flagged there if it failed) and R_H^T R_H enters
+// as Y^T Y (equal to rounding; the ks x s QR of Y is not formed).  Then
+// H_{k+1,k} = chol(R_W^T R_W - R_H^T R_H) (flag), H_{1:k,k} = Y and the
+// coefficients of V_{k+1} = (W - V_{1:k} Y) R^{-1}, as in BCGS-PIP.
+template <bool FIT>
+__global__ __launch_bounds__(NT) void small_pio_kernel(Dense d, int k, int force, int house) {
+  __shared__ double lds[LDS_DBL];
+  Ctl* ctl = d.ctl;
+  if (ctl->stop) return;
+  const int s = d.s, ld = d.ldh, ss = s * s, ks = k * s;
+  CoefLayout lay{s, d.mmax + 1};
+  double* RW = lds;
+  double* RH = RW + ss;
+  double* M = RH + ss;
+  double* R = M + ss;
+  double* Ri = R + ss;
+  double* dinv = Ri + ss;   // kMaxS
+  const int lused = 5 * ss + kMaxS;
+  const double* Gp;
+  if constexpr (FIT) {
+    bcopy(d.G, lds + lused, ks * s);
+    Gp = lds + lused;
+  } else {
+    Gp = d.G;
+  }
+  bar();
+  double* Hc = d.H + (int64_t)(k - 1) * s;
+  double* Hsub = Hc + (int64_t)ks * ld;   // H_{k+1,k}
+  bool ok = true;
+  if (house) {
+    for (int e = threadIdx.x; e < ss; e += NT) RW[e] = Hsub[(int64_t)(e / s) * ld + (e % s)];
+    bar();
+    // M = R_W^T R_W - Y^T Y
+    mm_t<true, false>(s, s, s, 1.0, RW, s, RW, s, 0.0, R, s);
+    bar();
+    mm_t<true, false>(s, s, ks, -1.0, Gp, s, Gp, s, 0.0, M, s, R, s);
+    bar();
+  } else {
+    ok = chol_flag(d, d.G2, s, RW);
+    if (ok) {
+      mm_t<true, false>(s, s, ks, 1.0, Gp, s, Gp, s, 0.0, M, s);   // Y^T Y
+      bar();
+      ok = chol_flag(d, M, s, RH);
+    }
+    if (ok) {
+      // M = R_W^T R_W - R_H^T R_H
+      mm_t<true, false>(s, s, s, 1.0, RW, s, RW, s, 0.0, R, s);
+      bar();
+      mm_t<true, false>(s, s, s, -1.0, RH, s, RH, s, 0.0, M, s, R, s);
+      bar();
+    }
+  }
+  if (ok) ok = chol_flag(d, M, s, R, dinv);
+  if (force) ok = false;
+  if (!ok) {
+    if (threadIdx.x == 0) raise_flag(ctl, k, k - 1);
+    return;
+  }
+  tri_inv_up(R, s, Ri, dinv);
+  double* coef = d.coef64;
+  for (int e = threadIdx.x; e < ss; e += NT) {
+    coef[lay.C2() + e] = Ri[e];
+    d.Rinv[e] = Ri[e];
+    Hsub[(int64_t)(e / s) * ld + (e % s)] = R[e];
+  }
+  for (int e = threadIdx.x; e < ks * s; e += NT) {
+    const int i = e / s, c = e % s;
+    const double* y = Gp + (int64_t)i * s;
+    double b = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < s; ++t) b = fma(y[t], Ri[t * s + c], b);
+    coef[lay.B(0) + e] = -b;
+    Hc[(int64_t)i * ld + c] = y[c];
+  }
+  bar();
+  publish_coef(d);
+}
+
 // Alg. 2 (BMGS), loop step k, inner step i (both 1-based): H_{i,k} = V_i^T W
 // (the Gram output) and the coefficients of W <- W - V_i H_{i,k}.
 __global__ __launch_bounds__(NT) void small_bmgs_kernel(Dense d, int k, int i) {
@@ -1184,6 +1266,14 @@ void launch_small_pip(hipStream_t st, const Dense& d, int k, int force_flag, KTi
     SMALL_LAUNCH(small_pip_kernel<true><<<1, NT, 0, st>>>(d, k, force_flag));
   else
     SMALL_LAUNCH(small_pip_kernel<false><<<1, NT, 0, st>>>(d, k, force_flag));
+}
+void launch_small_pio(hipStream_t st, const Dense& d, int k, int force_flag, int house,
+                      KTimer* tm) {
+  const int s = d.s;
+  if (k * s * s <= LDS_DBL - (5 * s * s + kMaxS))
+    SMALL_LAUNCH(small_pio_kernel<true><<<1, NT, 0, st>>>(d, k, force_flag, house));
+  else
+    SMALL_LAUNCH(small_pio_kernel<false><<<1, NT, 0, st>>>(d, k, force_flag, house));
 }
 void launch_small_bmgs(hipStream_t st, const Dense& d, int k, int i, KTimer* tm) {
   SMALL_LAUNCH(small_bmgs_kernel<<<1, NT, 0, st>>>(d, k, i));

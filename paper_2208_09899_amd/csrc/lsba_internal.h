@@ -237,6 +237,11 @@ void launch_small_svl_z(hipStream_t st, const Dense& d, int k, KTimer* tm = null
 // projection coefficients from [V_{1:k} W]^T W.
 void launch_small_pip(hipStream_t st, const Dense& d, int k, int force_flag,
                       KTimer* tm = nullptr);
+// Alg. 4 (BCGS-PIO), loop step k, after Y = V_{1:k}^T W and the IntraOrtho
+// of W (CholQR: W^T W in G2; HouseQR: R_W in H_{k+1,k}): H_{1:k,k},
+// H_{k+1,k} (flags) and the projection coefficients.
+void launch_small_pio(hipStream_t st, const Dense& d, int k, int force_flag, int house,
+                      KTimer* tm = nullptr);
 // Alg. 2 (BMGS), loop step k, inner step i: H_{i,k} = V_i^T W and the
 // coefficients of W <- W - V_i H_{i,k}.
 void launch_small_bmgs(hipStream_t st, const Dense& d, int k, int i, KTimer* tm = nullptr);

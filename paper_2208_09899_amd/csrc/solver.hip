@@ -229,6 +229,15 @@ void cycle_counts(int skel, int j, int status, int flag_step, int64_t& a, int64_
     v += 3 * full + 2 * partial;
     return;
   }
+  if (skel == LSBA_BCGS_PIO) {
+    // step k: one A-call, the inner product and the IntraOrtho (2 syncs),
+    // 2 basis applications (inner product, projection); a flagged step
+    // stops before its projection
+    a += full + partial;
+    sy += 2 * (full + partial);
+    v += 2 * full + partial;
+    return;
+  }
   if (skel == LSBA_BMGS) {
     // step k: one A-call, k block inner products and the IntraOrtho
     for (int k = 1; k <= full + partial; ++k) {
@@ -809,6 +818,35 @@ struct CycleRunner {
           launch_small_loo(st, d, kk + 1, tm);
         }
       }
+    } else if (p.skeleton == LSBA_BCGS_PIO) {
+      // Alg. 4: SpMM, the inner product V_{1:k}^T W, the IntraOrtho of W
+      // (CholQR Gram or TSQR, into a scratch block), the Pythagorean
+      // Cholesky from the two triangular factors, one projection
+      for (int kk = 1; kk <= m; ++kk) {
+        const int force = fk == kk ? 1 : 0;
+        tag(kk, 0);
+        launch_spmm<T>(st, n, op->nnz, s, op->rp, op->ci, val, slot(k, kk - 1), k.W, ctl, tm);
+        launch_gram<T>(st, gram_args<T>(k, kk, {}, {k.W}), k.partial, d.G, ctl, tm);
+        const int house = p.muscle == LSBA_HOUSEQR ? 1 : 0;
+        if (house)
+          launch_house<T>(st, d, n, s, k.W, k.U, (T*)nullptr, k.hwork, HM_IO, kk, 0, tm);
+        else
+          launch_gram<T>(st, gram_args<T>(k, 0, {k.W}, {k.W}), k.partial, d.G2, ctl, tm);
+        launch_small_pio(st, d, kk, force, house, tm);
+        tag(kk, 1);
+        finalize_after(kk, kk);
+        UpdateArgs<T> u = upd_args(k);
+        u.in2 = k.W;
+        u.out2 = slot(k, kk);
+        u.nv2_begin = 0;
+        u.nv2 = kk;
+        launch_update<T>(st, u, ctl, true, tm);
+        if (rec_loo) {
+          launch_gram<T>(st, gram_args<T>(k, kk + 1, {}, {slot(k, kk)}), k.partial, d.G2, ctl,
+                         tm);
+          launch_small_loo(st, d, kk + 1, tm);
+        }
+      }
     } else if (p.skeleton == LSBA_BMGS) {
       // Alg. 2: SpMM, then for i = 1..k one inner product V_i^T W and one
       // subtraction each (in place on W), then the IntraOrtho of W
@@ -1093,7 +1131,7 @@ void validate_params(const lsba_params* p, int s) {
   if (s < 1 || s > kMaxS) throw ArgError{"s must be in [1, 32]"};
   if (p->m < 1 || p->m > kMaxM) throw ArgError{"m must be in [1, 128]"};
   if (p->method != LSBA_FOM && p->method != LSBA_GMRES) throw ArgError{"bad method"};
-  if (p->skeleton < LSBA_BCGSI_LS || p->skeleton > LSBA_BMGS) throw ArgError{"bad skeleton"};
+  if (p->skeleton < LSBA_BCGSI_LS || p->skeleton > LSBA_BCGS_PIO) throw ArgError{"bad skeleton"};
   if (p->muscle != LSBA_CHOLQR && p->muscle != LSBA_HOUSEQR) throw ArgError{"bad muscle"};
   if (p->precision != LSBA_FP64 && p->precision != LSBA_MIXED) throw ArgError{"bad precision"};
   if (!(p->tol >= 0.0)) throw ArgError{"tol must be >= 0"};

@@ -11,7 +11,7 @@ from gpu_common import pip_hist_atol, assert_parity, gpu_solve, oracle_solve
 
 pytestmark = pytest.mark.gpu
 
-SKELETONS = ["bcgsi_ls", "bmgs_svl", "bmgs_lts", "bmgs_cwy", "bmgs_icwy", "bcgs_pip", "bmgs"]
+SKELETONS = ["bcgsi_ls", "bmgs_svl", "bmgs_lts", "bmgs_cwy", "bmgs_icwy", "bcgs_pip", "bmgs", "bcgs_pio"]
 
 
 @pytest.mark.parametrize("method", ["fom", "gmres"])
@@ -21,7 +21,7 @@ def test_houseqr_laplace2d_32(method, skel):
     g = gpu_solve(wl.A, wl.B, method=method, skeleton=skel, muscle="houseqr", m=30, tol=1e-8,
                   max_cycles=1000)
     o = oracle_solve(wl.A, wl.B, method, skel, m=30, tol=1e-8, max_cycles=1000, muscle="houseqr")
-    assert_parity(g, o, hist_atol=pip_hist_atol(440.0) if skel == "bcgs_pip" else 1e-12)
+    assert_parity(g, o, hist_atol=pip_hist_atol(440.0) if skel in ("bcgs_pip", "bcgs_pio") else 1e-12)
 
 
 @pytest.mark.parametrize("skel", ["bcgsi_ls", "bmgs_svl", "bmgs_cwy"])

@@ -10,7 +10,7 @@ from gpu_common import pip_hist_atol, assert_parity, gpu_solve, oracle_solve
 
 pytestmark = pytest.mark.gpu
 
-SKELETONS = ["bcgsi_ls", "bmgs_svl", "bmgs_lts", "bmgs_cwy", "bmgs_icwy", "bcgs_pip", "bmgs"]
+SKELETONS = ["bcgsi_ls", "bmgs_svl", "bmgs_lts", "bmgs_cwy", "bmgs_icwy", "bcgs_pip", "bmgs", "bcgs_pio"]
 
 
 def test_tridiag1000_gmres_bcgsi_ls_capped_at_50_cycles():
@@ -32,7 +32,7 @@ def test_laplace2d_32_all_skeletons(method, skel):
     g = gpu_solve(wl.A, wl.B, method=method, skeleton=skel, m=30, tol=1e-8, max_cycles=1000)
     o = oracle_solve(wl.A, wl.B, method, skel, m=30, tol=1e-8, max_cycles=1000)
     kappa = 440.0
-    assert_parity(g, o, hist_atol=pip_hist_atol(kappa) if skel == "bcgs_pip" else 1e-12)
+    assert_parity(g, o, hist_atol=pip_hist_atol(kappa) if skel in ("bcgs_pip", "bcgs_pio") else 1e-12)
 
 
 @pytest.mark.parametrize("skel", SKELETONS)
@@ -71,7 +71,8 @@ def test_forced_flag_adaptive_restart_matches(skel):
 
 
 @pytest.mark.parametrize("skel,step", [("bcgsi_ls", 0), ("bcgsi_ls", 2), ("bmgs_cwy", 2),
-                                       ("bmgs_svl", 1), ("bcgs_pip", 1), ("bmgs", 1)])
+                                       ("bmgs_svl", 1), ("bcgs_pip", 1), ("bmgs", 1),
+                                       ("bcgs_pio", 1)])
 def test_breakdown_without_final_column(skel, step):
     A = w.laplace_1d(200)
     B = w.rhs(200, 2, 1)
