@@ -51,9 +51,11 @@ WORKLOADS = {
 }
 
 # HBM traffic of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# runs scaled by the same counters on a plain copy of known size (see
-# profiles/traffic.json); only used while the kernel source is unchanged.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+# runs scaled by the same counters on a plain copy of known size (one record
+# per workload, profiles/traffic_<workload>.json); only used while the kernel
+# source is unchanged.
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
 KERNEL_SOURCES = {"update": "kernels_update.hip", "gram": "kernels_gram.hip",
                   "spmm": "kernels_sparse.hip"}
 
@@ -68,7 +70,7 @@ def stored_traffic(kind, workload):
     """Calibrated HBM bytes per launch of kernel class `kind` on `workload`, or
     None when no measurement of the current source exists."""
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(traffic_file(workload)))
     except (OSError, ValueError):
         return None
     k = rec.get("kernels", {}).get(kind)
@@ -351,10 +353,16 @@ def main():
     if "roofline" in line:
         tr = stored_traffic(line["roofline"]["kernel"], args.workload)
         if tr:
-            line["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
+            # the counter run covers a capped solve (other launch sizes than the
+            # timed one), so its calibrated traffic / algorithmic bytes ratio is
+            # applied to this run's algorithmic bytes per launch
+            ab = line["roofline"]["alg_bytes_per_launch"]
+            line["roofline"]["traffic"] = tr["traffic_over_alg"] * ab if ab else None
             line["roofline"]["traffic_note"] = (
-                f"calibrated FETCH_SIZE+WRITE_SIZE per launch over {tr['launches']} launches "
-                f"(algorithmic bytes per launch in that run {tr['alg_bytes_per_launch']:.4g})")
+                f"calibrated FETCH_SIZE+WRITE_SIZE / algorithmic bytes = "
+                f"{tr['traffic_over_alg']:.3f} over {tr['launches']} launches of a capped run "
+                f"(profiles/traffic_{args.workload}.json), times this run's algorithmic bytes "
+                f"per launch")
     if precision == "fp64" and not args.no_mixed and len(solves) == 1:
         # the precision form on the same problem, beside the headline (not in
         # the timed region): time to the same tolerance, true residual, and
