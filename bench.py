@@ -38,6 +38,8 @@ FP32_PEAK_TFS = 157.3      # MI355X FP32 vector peak (published)
 BF16_PEAK_TFS = 2500.0     # MI355X dense BF16 matrix peak (published, no sparsity)
 BF16_SPLIT_PRODUCTS = 6    # FP32 products as six BF16 part products (three-part splits)
 
+RGG_ITER_BUDGET = 500      # block iterations per solve on the random geometric graph
+
 WORKLOADS = {
     # name: (workload key, scale, solve list [(method, skeleton)], precision, s, note)
     "laplace2d": ("laplace2d", None,
@@ -83,10 +85,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, solves, gpu_iters, budget_s=15.0):
+def cpu_baseline(wl, solves, gpu_iters, budget_s=15.0, per_iteration=False):
     """Time the oracle on the host for a bounded number of block iterations of
     the first configured solve and scale to solves/s with the GPU's (identical)
-    iteration counts."""
+    iteration counts (or report block iterations/s for a budgeted workload)."""
     import threadpoolctl
 
     import oracle
@@ -110,8 +112,8 @@ def cpu_baseline(wl, solves, gpu_iters, budget_s=15.0):
         if info.get("internal_api") in ("openblas", "mkl", "blis"):
             threads = max(threads, int(info.get("num_threads", 1)))
     return {
-        "value": len(solves) / step_s,
-        "unit": "solves/s",
+        "value": 1.0 / per_iter if per_iteration else len(solves) / step_s,
+        "unit": "block-iterations/s" if per_iteration else "solves/s",
         "cores": threads,
         "kind": "oracle",
         "sample": (f"{r.iters} block iterations of {method}/{skel} (m={wl.m}) in {dt:.1f} s "
@@ -230,6 +232,13 @@ def main():
     ctx = lsba.Context(0, stream="torch")
     op = lsba.Operator(ctx, wl.A)
     kw = dict(m=wl.m, tol=wl.tol, max_cycles=wl.max_cycles, precision=precision)
+    # the random geometric graph of mean degree 4 lies below the 2-D
+    # percolation threshold: many components with eigenvalues at the 1e-6
+    # shift, and restarted BGMRES(25) does not reach 1e-8 in benchmark time,
+    # so it runs over a fixed budget of block iterations and reports their rate
+    budget = RGG_ITER_BUDGET if key == "rgg" else 0
+    if budget:
+        kw["max_iters"] = budget
 
     def step():
         out = []
@@ -276,6 +285,10 @@ def main():
     elapsed = t1 - t0
     nsolves = len(solves) * args.steps
     value = nsolves / elapsed
+    unit = "solves/s"
+    if budget:
+        value = sum(r.iters for _, _, r in last) * args.steps / elapsed
+        unit = "block-iterations/s"
     res = []
     for method, skel, r in last:
         res.append({"method": method, "skeleton": skel, "status": r.status, "iters": r.iters,
@@ -284,7 +297,7 @@ def main():
     line = {
         "metric": METRIC,
         "value": value,
-        "unit": "solves/s",
+        "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -294,7 +307,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": wl.note, "n": n, "s": s, "m": wl.m, "tol": wl.tol,
+        "config": {"workload": wl.note + (f", budget of {budget} block iterations per solve"
+                                          if budget else ""),
+                   "n": n, "s": s, "m": wl.m, "tol": wl.tol,
                    "solves_per_step": [f"{m}/{k}" for m, k in solves],
                    "nnz": wl.A.nnz},
         "solves": res,
@@ -363,7 +378,7 @@ def main():
                 f"{tr['traffic_over_alg']:.3f} over {tr['launches']} launches of a capped run "
                 f"(profiles/traffic_{args.workload}.json), times this run's algorithmic bytes "
                 f"per launch")
-    if precision == "fp64" and not args.no_mixed and len(solves) == 1:
+    if precision == "fp64" and not args.no_mixed and len(solves) == 1 and not budget:
         # the precision form on the same problem, beside the headline (not in
         # the timed region): time to the same tolerance, true residual, and
         # its difference from the FP64 solution just computed
@@ -386,7 +401,8 @@ def main():
         }
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample ...")
-        line["cpu_baseline"] = cpu_baseline(wl, solves, [r["iters"] for r in res])
+        line["cpu_baseline"] = cpu_baseline(wl, solves, [r["iters"] for r in res],
+                                            per_iteration=bool(budget))
     print(json.dumps(line), flush=True)
     op.close()
     ctx.close()
