@@ -77,7 +77,11 @@ typedef enum {
   LSBA_BCGS_PIO = 7           /* Alg. 4, inner product + IntraOrtho of [W 0; 0 H]: 2 syncs/step */
 } lsba_skeleton;
 
-typedef enum { LSBA_CHOLQR = 0, LSBA_HOUSEQR = 1 } lsba_muscle;
+/* LSBA_GLOBAL selects the global block paradigm as a whole (Sec. 2.2,
+   Table 1): every block inner product is (1/s) trace(X^T Y) I_s and the
+   muscle is the global scaling ||X||_F / sqrt(s) I_s (the paper forces that
+   muscle in the global paradigm).  Not available with LSBA_BCGS_PIO. */
+typedef enum { LSBA_CHOLQR = 0, LSBA_HOUSEQR = 1, LSBA_GLOBAL = 2 } lsba_muscle;
 
 typedef enum {
   LSBA_FP64 = 0,              /* every step in FP64                                        */

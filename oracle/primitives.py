@@ -18,6 +18,21 @@ def ip(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
     return X.T @ Y
 
 
+def ip_global(X: np.ndarray, Y: np.ndarray, s: int) -> np.ndarray:
+    """Global block inner product (Sec. 2.2, Table 1): for n x s block vectors
+    <X, Y> = (1/s) trace(X^T Y) I_s.  For concatenations [X_1 .. X_p] and
+    [Y_1 .. Y_q] the result is the p s x q s matrix of the pairwise global
+    products (each s x s block a multiple of I_s)."""
+    G = X.T @ Y
+    p, q = G.shape[0] // s, G.shape[1] // s
+    out = np.zeros_like(G)
+    for i in range(p):
+        for j in range(q):
+            t = np.trace(G[i * s:(i + 1) * s, j * s:(j + 1) * s]) / s
+            out[i * s:(i + 1) * s, j * s:(j + 1) * s] = t * np.eye(s)
+    return out
+
+
 def chol_flag(Om: np.ndarray):
     """Cholesky factor with a breakdown flag (Sec. 4, the ``chol`` variant that
     raises the NaN-flag instead of failing).
@@ -80,16 +95,34 @@ def houseqr(X: np.ndarray):
     return Q, R, ok
 
 
+def global_muscle(X: np.ndarray):
+    """The global paradigm's muscle (Sec. 2.2, Table 1): N(X) = ||X||_F /
+    sqrt(s) I_s, Q = X N(X)^{-1} -- a scaling, no intra-orthogonalization.
+    It is CholQR under the global inner product (the Cholesky factor of
+    (1/s) ||X||_F^2 I_s); the flag is raised when ||X||_F^2 is not a positive
+    finite number.  Returns (Q, R, ok)."""
+    s = X.shape[1]
+    nu2 = float(np.sum(X * X)) / s
+    if not np.isfinite(nu2) or nu2 <= 0.0:
+        return None, np.zeros((s, s)), False
+    nu = math.sqrt(nu2)
+    return X / nu, nu * np.eye(s), True
+
+
 def intra_ortho(X: np.ndarray, muscle: str):
     """IntraOrtho(X) -> (Q, R, T, ok).  T is the auxiliary factor the
     SVL/LTS skeletons expect from the muscle (Alg. 5, lines 2 and 7).
 
-    Reading: CholQR and HouseQR carry no such factor; T = I_s, its value for
-    an exactly orthonormal Q."""
+    Reading: CholQR, HouseQR and the global muscle carry no such factor;
+    T = I_s, its value for an exactly orthonormal Q.  muscle = "global"
+    selects the global paradigm as a whole (the skeletons then use the global
+    inner product too; the paper forces the global muscle there, Sec. 5)."""
     if muscle == "cholqr":
         Q, R, ok = cholqr(X)
     elif muscle == "houseqr":
         Q, R, ok = houseqr(X)
+    elif muscle == "global":
+        Q, R, ok = global_muscle(X)
     else:
         raise ValueError(f"unknown muscle {muscle!r}")
     return Q, R, np.eye(X.shape[1]), ok

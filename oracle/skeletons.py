@@ -28,7 +28,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-from .primitives import chol_flag, intra_ortho, ip, left_solve_upper_t, right_solve_upper
+from .primitives import chol_flag, intra_ortho, ip, ip_global, left_solve_upper_t, right_solve_upper
 
 
 class Counters:
@@ -71,6 +71,13 @@ class _Skeleton:
         """[V_1 ... V_i] as an n x is array."""
         return np.hstack(self.V[:i])
 
+    def ip(self, X, Y):
+        """The block inner product of the paradigm (Sec. 2.2, Table 1):
+        classical X^T Y, or the global one when the muscle is "global"."""
+        if self.muscle == "global":
+            return ip_global(X, Y, self.s)
+        return ip(X, Y)
+
     def matvec(self, X):
         self.ct.a_calls += 1
         return self.A @ X
@@ -108,7 +115,7 @@ class BMGS(_Skeleton):
             W = self.matvec(self.V[k - 1])
             for i in range(1, k + 1):
                 self.ct.syncs += 1
-                H[self.blk(i), self.blk(k)] = ip(self.V[i - 1], W)
+                H[self.blk(i), self.blk(k)] = self.ip(self.V[i - 1], W)
                 W = W - self.V[i - 1] @ H[self.blk(i), self.blk(k)]
             self.ct.v_apps += 2
             self.ct.syncs += 1
@@ -139,7 +146,7 @@ class BCGS_PIP(_Skeleton):
             Vk = self.Vcat(k)
             self.ct.syncs += 1
             self.ct.v_apps += 2
-            G = ip(np.hstack([Vk, W]), W)
+            G = self.ip(np.hstack([Vk, W]), W)
             Hk = G[: k * s]
             Om = G[k * s:]
             H[self.upto(k), self.blk(k)] = Hk
@@ -165,6 +172,8 @@ class BCGS_PIO(_Skeleton):
     columns."""
 
     def run(self, R0):
+        if self.muscle == "global":
+            raise ValueError("BCGS-PIO is defined for the classical paradigm only")
         V1, self.Beta, _, ok = self.start(R0)
         if not ok:
             self.flagged, self.last = True, 0
@@ -176,7 +185,7 @@ class BCGS_PIO(_Skeleton):
             Vk = self.Vcat(k)
             self.ct.syncs += 1
             self.ct.v_apps += 1
-            Hk = ip(Vk, W)
+            Hk = self.ip(Vk, W)
             H[self.upto(k), self.blk(k)] = Hk
             n = W.shape[0]
             D = np.zeros((n + k * s, 2 * s))
@@ -226,7 +235,7 @@ class BMGS_SVL(_Skeleton):
             Vk = self.Vcat(k)
             self.ct.syncs += 1
             self.ct.v_apps += 1
-            Y = ip(Vk, W)
+            Y = self.ip(Vk, W)
             Tk = T[self.upto(k), self.upto(k)]
             if self.lts:
                 Hk = sla.solve_triangular(Tk.T, Y, lower=True, check_finite=False)
@@ -243,7 +252,7 @@ class BMGS_SVL(_Skeleton):
             self.V.append(Q)
             self.ct.syncs += 1
             self.ct.v_apps += 1
-            Z = ip(Vk, Q)
+            Z = self.ip(Vk, Q)
             if self.lts:
                 T[self.upto(k), self.blk(k + 1)] = Z @ Tkk
             else:
@@ -286,14 +295,14 @@ class BMGS_CWY(_Skeleton):
             W = self.matvec(U)
             if k == 1:
                 self.ct.syncs += 1
-                H[self.blk(1), self.blk(1)] = ip(U, W)
+                H[self.blk(1), self.blk(1)] = self.ip(U, W)
                 self.ct.v_apps += 1
                 U = W - self.V[0] @ H[self.blk(1), self.blk(1)]
                 continue
             Vkm1 = self.Vcat(k - 1)
             self.ct.syncs += 1
             self.ct.v_apps += 2
-            G = ip(np.hstack([Vkm1, U]), np.hstack([U, W]))
+            G = self.ip(np.hstack([Vkm1, U]), np.hstack([U, W]))
             Y, Z = G[: (k - 1) * s, :s], G[: (k - 1) * s, s:]
             Om, Pt = G[(k - 1) * s:, :s], G[(k - 1) * s:, s:]
             R, ok = self.chol(Om, k)
@@ -348,7 +357,7 @@ class BCGSI_LS(_Skeleton):
             W = self.matvec(U)
             if k == 1:
                 self.ct.syncs += 1
-                J = ip(U, W)
+                J = self.ip(U, W)
                 H[self.blk(1), self.blk(1)] = J
                 self.ct.v_apps += 1
                 U = W - self.V[0] @ J
@@ -356,7 +365,7 @@ class BCGSI_LS(_Skeleton):
             Vkm1 = self.Vcat(k - 1)
             self.ct.syncs += 1
             self.ct.v_apps += 2
-            G = ip(np.hstack([Vkm1, U]), np.hstack([U, W]))
+            G = self.ip(np.hstack([Vkm1, U]), np.hstack([U, W]))
             Y, Z = G[: (k - 1) * s, :s], G[: (k - 1) * s, s:]
             Omt, Pt = G[(k - 1) * s:, :s], G[(k - 1) * s:, s:]
             Om = Omt - Y.T @ Y

@@ -131,7 +131,7 @@ def solve(A, B, method: str = "gmres", skeleton: str = "bcgsi_ls", muscle: str =
             res_hist.append(est / nB)
             if record_loo:
                 Vc = sk.Vcat(j + 1)
-                loo_hist.append(float(np.linalg.norm(np.eye((j + 1) * s) - Vc.T @ Vc, 2)))
+                loo_hist.append(float(np.linalg.norm(np.eye((j + 1) * s) - sk.ip(Vc, Vc), 2)))
             if x_star is None:
                 crit = est / nB
             elif Xi is None:

@@ -768,9 +768,47 @@ int distinct_blocks(const GramArgs<T>& a) {
   return cnt;
 }
 
+// The global paradigm's block inner product (Sec. 2.2, Table 1): each s x s
+// block of the reduced Gram becomes (1/s) trace(block) I_s.  One wavefront
+// per block; the diagonal is summed by a fixed butterfly (s <= 32), so the
+// result does not depend on timing.
+__global__ __launch_bounds__(64) void gram_globalize(double* __restrict__ out, int s, int QB,
+                                                     const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->stop) return;
+  const int nbj = QB / s;
+  const int bi = blockIdx.x / nbj, bj = blockIdx.x % nbj;
+  double* blk = out + (int64_t)bi * s * QB + (int64_t)bj * s;
+  const int l = threadIdx.x;
+  double v = l < s ? blk[(int64_t)l * QB + l] : 0.0;
+  // butterfly over the whole wavefront: every lane holds the sum (lanes
+  // 32..63 write entries too once s * s > 32)
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  const double t = v / s;
+  for (int e = l; e < s * s; e += 64) {
+    const int r = e / s, c = e % s;
+    blk[(int64_t)r * QB + c] = r == c ? t : 0.0;
+  }
+}
+
+template <typename T>
+void launch_gram_classical(hipStream_t st, const GramArgs<T>& a, double* partial, double* out,
+                           const Ctl* ctl, KTimer* tm);
+
 template <typename T>
 void launch_gram(hipStream_t st, const GramArgs<T>& a, double* partial, double* out,
                  const Ctl* ctl, KTimer* tm) {
+  launch_gram_classical<T>(st, a, partial, out, ctl, tm);
+  if (a.glob) {
+    const int PA = (a.nv + a.nxl) * a.s, QB = a.nxr * a.s;
+    launch_k(tm, KK_GRAM_REDUCE, 0.0, gram_globalize, dim3((PA / a.s) * (QB / a.s)), dim3(64),
+             0, st, out, a.s, QB, ctl);
+  }
+}
+
+template <typename T>
+void launch_gram_classical(hipStream_t st, const GramArgs<T>& a, double* partial, double* out,
+                           const Ctl* ctl, KTimer* tm) {
   const int PA = (a.nv + a.nxl) * a.s, QB = a.nxr * a.s;
   const double gflops = 2.0 * (double)a.n * PA * QB;
   if constexpr (sizeof(T) == sizeof(float)) {

@@ -60,6 +60,8 @@ struct Dense {
   int skel;       // lsba_skeleton
   int method;     // lsba_method
   int mixed;      // 1: shifted-Cholesky fallback allowed (mixed form)
+  int glob;       // 1: global block paradigm (every Gram block -> (1/s) tr I_s)
+  int pad0;       // keeps the struct free of padding bytes (always 0)
   double* H;      // block Hessenberg, (mmax + 2) s rows x ldh
   double* T;      // auxiliary T of Algs. 5 / 6, ldh x ldh
   double* Tt;     // its transpose (kept so that products read rows), ldh x ldh
@@ -186,6 +188,7 @@ struct GramArgs {
   int nxl;
   const T* xr[2];    // right blocks
   int nxr;
+  int glob;          // global paradigm: each s x s block of the result -> (1/s) trace I_s
 };
 size_t gram_partial_doubles(int64_t n, int s, int nleft, int nright);
 template <typename T>

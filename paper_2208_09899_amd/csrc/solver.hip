@@ -448,6 +448,8 @@ Krylov<T> make_krylov_with(Alloc&& alloc, int64_t n, int s, int m, const lsba_pa
   d.mmax = m;
   d.ldh = ldh;
   d.skel = p.skeleton;
+  d.glob = p.muscle == LSBA_GLOBAL ? 1 : 0;
+  d.pad0 = 0;
   d.method = p.method;
   d.mixed = sizeof(T) == sizeof(float) ? 1 : 0;
   d.gstride = per_step ? (long long)gslot : 0;
@@ -500,6 +502,7 @@ GramArgs<T> gram_args(const Krylov<T>& k, int nv, std::initializer_list<const T*
   for (const T* p : xl) g.xl[g.nxl++] = p;
   g.nxr = 0;
   for (const T* p : xr) g.xr[g.nxr++] = p;
+  g.glob = k.d.glob;
   return g;
 }
 
@@ -1132,7 +1135,10 @@ void validate_params(const lsba_params* p, int s) {
   if (p->m < 1 || p->m > kMaxM) throw ArgError{"m must be in [1, 128]"};
   if (p->method != LSBA_FOM && p->method != LSBA_GMRES) throw ArgError{"bad method"};
   if (p->skeleton < LSBA_BCGSI_LS || p->skeleton > LSBA_BCGS_PIO) throw ArgError{"bad skeleton"};
-  if (p->muscle != LSBA_CHOLQR && p->muscle != LSBA_HOUSEQR) throw ArgError{"bad muscle"};
+  if (p->muscle != LSBA_CHOLQR && p->muscle != LSBA_HOUSEQR && p->muscle != LSBA_GLOBAL)
+    throw ArgError{"bad muscle"};
+  if (p->muscle == LSBA_GLOBAL && p->skeleton == LSBA_BCGS_PIO)
+    throw ArgError{"BCGS-PIO is defined for the classical paradigm only"};
   if (p->precision != LSBA_FP64 && p->precision != LSBA_MIXED) throw ArgError{"bad precision"};
   if (!(p->tol >= 0.0)) throw ArgError{"tol must be >= 0"};
   if (p->max_cycles < 1) throw ArgError{"max_cycles must be >= 1"};

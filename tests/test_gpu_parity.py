@@ -70,6 +70,39 @@ def test_forced_flag_adaptive_restart_matches(skel):
     assert g.m_after[0] < 10
 
 
+GLOBAL_SKELETONS = [k for k in SKELETONS if k != "bcgs_pio"]
+
+
+@pytest.mark.parametrize("method", ["fom", "gmres"])
+@pytest.mark.parametrize("skel", GLOBAL_SKELETONS)
+def test_global_paradigm_laplace2d_32(method, skel):
+    """The global block paradigm (Sec. 2.2, Table 1: (1/s) trace inner
+    product, global muscle) against the oracle's, every skeleton but PIO."""
+    wl = w.workload("laplace2d", 32)
+    g = gpu_solve(wl.A, wl.B, method=method, skeleton=skel, muscle="global", m=30, tol=1e-8,
+                  max_cycles=1000)
+    o = oracle_solve(wl.A, wl.B, method, skel, m=30, tol=1e-8, max_cycles=1000, muscle="global")
+    assert_parity(g, o, hist_atol=pip_hist_atol(440.0) if skel == "bcgs_pip" else 1e-12)
+
+
+@pytest.mark.parametrize("skel", ["bcgsi_ls", "bmgs_svl", "bmgs_icwy", "bmgs"])
+@pytest.mark.parametrize("s", [1, 3, 8, 16])
+def test_global_paradigm_convdiff_ragged(skel, s):
+    A = w.convdiff_2d(45, 3.0, 0.7)
+    B = w.rhs(A.n, s, seed=31 + s)
+    g = gpu_solve(A, B, method="gmres", skeleton=skel, muscle="global", m=12, tol=1e-9,
+                  max_cycles=300)
+    o = oracle_solve(A, B, "gmres", skel, m=12, tol=1e-9, max_cycles=300, muscle="global")
+    assert_parity(g, o)
+
+
+def test_global_paradigm_rejected_for_pio():
+    A = w.laplace_1d(50)
+    B = w.rhs(50, 2, 1)
+    with pytest.raises(Exception):
+        gpu_solve(A, B, skeleton="bcgs_pio", muscle="global", m=5)
+
+
 @pytest.mark.parametrize("skel,step", [("bcgsi_ls", 0), ("bcgsi_ls", 2), ("bmgs_cwy", 2),
                                        ("bmgs_svl", 1), ("bcgs_pip", 1), ("bmgs", 1),
                                        ("bcgs_pio", 1)])
@@ -135,14 +168,27 @@ def test_paper_tridiag_counts_on_gpu():
               "bcgsi_ls": (94, [70, 24], (96, 378, 98)),
               "bmgs": (94, [70, 24], (94, 188, 2881)),
               "bcgs_pip": (172, [70, 70, 32], (172, 516, 175))}
-    for skel, (iters, cycles, counts) in expect.items():
-        g = gpu_solve(A, B, method="fom", skeleton=skel, m=70, tol=0.0, max_cycles=10,
-                      max_iters=iters)
-        o = oracle_solve(A, B, "fom", skel, m=70, tol=0.0, max_cycles=10, max_iters=iters)
+    # the global paradigm's rows: 621 iterations in 9 cycles
+    gl = [70] * 8 + [61]
+    expect_gl = {"gl-bmgs": (621, gl, (621, 1242, 22401)),
+                 "gl-bmgs_svl": (621, gl, (621, 1863, 1872)),
+                 "gl-bmgs_lts": (621, gl, (621, 1863, 1872)),
+                 "gl-bcgsi_ls": (621, gl, (630, 2493, 639)),
+                 "gl-bmgs_cwy": (621, gl, (630, 1872, 639)),
+                 "gl-bmgs_icwy": (621, gl, (630, 1872, 639)),
+                 "gl-bcgs_pip": (621, gl, (621, 1863, 630))}
+    expect.update(expect_gl)
+    for name, (iters, cycles, counts) in expect.items():
+        skel = name[3:] if name.startswith("gl-") else name
+        mu = "global" if name.startswith("gl-") else "cholqr"
+        g = gpu_solve(A, B, method="fom", skeleton=skel, muscle=mu, m=70, tol=0.0,
+                      max_cycles=10, max_iters=iters)
+        o = oracle_solve(A, B, "fom", skel, m=70, tol=0.0, max_cycles=10, max_iters=iters,
+                         muscle=mu)
         h, ho = np.asarray(g.res_hist[:6]), np.asarray(o.res_hist[:6])
         assert np.all(np.abs(h - ho) <= 1e-8 * ho)
         assert g.iters == iters
-        if skel == "bcgs_pip":
+        if name == "bcgs_pip":
             # BCGS-PIP's basis loses orthogonality completely on this operator
             # (LOO reaches 1 by column ~35 in the FP64 oracle, checked on the
             # CPU), after which whether chol(Omega - Y^T Y) succeeds is decided
@@ -160,9 +206,9 @@ def test_paper_tridiag_counts_on_gpu():
             if nflag == 0:
                 assert list(g.cycle_len) == cycles and tuple(g.counts) == counts
             continue
-        assert list(g.cycle_len) == cycles, (skel, g.cycle_len)
-        assert tuple(g.counts) == counts, (skel, g.counts)
-        assert np.linalg.norm(g.X - o.X) / np.linalg.norm(o.X) <= 1e-10
+        assert list(g.cycle_len) == cycles, (name, g.cycle_len)
+        assert tuple(g.counts) == counts, (name, g.counts)
+        assert np.linalg.norm(g.X - o.X) / np.linalg.norm(o.X) <= 1e-10, name
 
 
 @pytest.mark.parametrize("skel", ["bcgsi_ls", "bmgs_cwy", "bmgs_svl"])

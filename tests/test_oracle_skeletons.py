@@ -151,3 +151,29 @@ def test_pio_equals_pip_on_a_well_conditioned_cycle():
     pio, _ = _cycle("bcgs_pio", A, B, 3)
     assert np.linalg.norm(pio.Hm1m(3) - pip.Hm1m(3)) <= 1e-11 * np.linalg.norm(pip.Hm1m(3))
     assert np.linalg.norm(pio.Vcat(4) - pip.Vcat(4)) <= 1e-11
+
+
+@pytest.mark.parametrize("name", ["bmgs", "bmgs_svl", "bmgs_lts", "bmgs_cwy", "bmgs_icwy",
+                                  "bcgsi_ls", "bcgs_pip"])
+def test_global_paradigm_arnoldi_relation(name):
+    """Global paradigm (Sec. 2.2, Table 1): A V_j = V_{j+1} H_{j+1,j} holds,
+    the basis is orthonormal in the global inner product
+    ((1/s) trace(V_i^T V_k) = delta_ik), and every s x s block of H is a
+    multiple of I_s."""
+    from oracle.primitives import ip_global
+    A = w.convdiff_2d(20, 4.0, 0.5).to_scipy()
+    B = w.rhs(400, 3, 17)
+    sk, j = _cycle(name, A, B, 10, muscle="global")
+    assert j == 10
+    s = 3
+    V = sk.Vcat(j + 1)
+    H = sk.Hm1m(j)
+    AV = A @ sk.Vcat(j)
+    assert np.linalg.norm(AV - V @ H) <= 1e-12 * np.linalg.norm(AV)
+    G = ip_global(V, V, s)
+    tol = 1e-7 if name == "bcgs_pip" else 1e-12
+    assert np.linalg.norm(np.eye(V.shape[1]) - G, 2) <= tol
+    for a in range(j + 1):
+        for b in range(j):
+            blk = H[a * s:(a + 1) * s, b * s:(b + 1) * s]
+            assert np.allclose(blk, blk[0, 0] * np.eye(s), rtol=0, atol=1e-14 * (1 + abs(blk[0, 0])))
