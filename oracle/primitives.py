@@ -109,6 +109,48 @@ def global_muscle(X: np.ndarray):
     return X / nu, nu * np.eye(s), True
 
 
+def mgs_lowsync(X: np.ndarray, lts: bool):
+    """Column-wise MGS-SVL / MGS-LTS muscles (Sec. 5 list of muscles; the
+    column versions of Alg. 5): for column j, y = Q_{1:j-1}^T x_j,
+    h = T^T y (SVL) or T^{-T} y (LTS), w = x_j - Q h, r = ||w|| (from w^T w),
+    q_j = w / r, then z = Q_{1:j-1}^T q_j and the new column of T,
+    -T z (SVL) or z (LTS), with T_jj = 1.  Syncs: 1 for the first column and
+    3 for each later one, 3 s - 2 per call.  The flag is raised when some
+    w^T w is not a positive finite number.  Returns (Q, R, T, ok)."""
+    n, s = X.shape
+    Q = np.zeros((n, s))
+    R = np.zeros((s, s))
+    T = np.eye(s)
+    for j in range(s):
+        x = X[:, j]
+        if j > 0:
+            y = Q[:, :j].T @ x
+            Tj = T[:j, :j]
+            h = sla.solve_triangular(Tj.T, y, lower=True, check_finite=False) if lts else Tj.T @ y
+            w = x - Q[:, :j] @ h
+            R[:j, j] = h
+        else:
+            w = x
+        rr = float(w @ w)
+        if not np.isfinite(rr) or rr <= 0.0:
+            return None, R, T, False
+        r = math.sqrt(rr)
+        R[j, j] = r
+        Q[:, j] = w / r
+        if j > 0:
+            z = Q[:, :j].T @ Q[:, j]
+            T[:j, j] = z if lts else -(T[:j, :j] @ z)
+    return Q, R, T, True
+
+
+def muscle_syncs(muscle: str, s: int) -> int:
+    """Syncs of one IntraOrtho call: one block inner product for CholQR,
+    HouseQR (TSQR) and the global muscle; 3 s - 2 for the column-wise MGS
+    muscles (Sec. 5 counts syncs inside the muscles; the appendix's totals
+    imply 3 s - 2 = 1 + 3 (s - 1))."""
+    return 3 * s - 2 if muscle in ("mgs_svl", "mgs_lts") else 1
+
+
 def intra_ortho(X: np.ndarray, muscle: str):
     """IntraOrtho(X) -> (Q, R, T, ok).  T is the auxiliary factor the
     SVL/LTS skeletons expect from the muscle (Alg. 5, lines 2 and 7).
@@ -123,6 +165,8 @@ def intra_ortho(X: np.ndarray, muscle: str):
         Q, R, ok = houseqr(X)
     elif muscle == "global":
         Q, R, ok = global_muscle(X)
+    elif muscle in ("mgs_svl", "mgs_lts"):
+        return mgs_lowsync(X, muscle == "mgs_lts")
     else:
         raise ValueError(f"unknown muscle {muscle!r}")
     return Q, R, np.eye(X.shape[1]), ok

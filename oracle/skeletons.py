@@ -28,7 +28,8 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-from .primitives import chol_flag, intra_ortho, ip, ip_global, left_solve_upper_t, right_solve_upper
+from .primitives import (chol_flag, intra_ortho, ip, ip_global, left_solve_upper_t, muscle_syncs,
+                         right_solve_upper)
 
 
 class Counters:
@@ -89,7 +90,7 @@ class _Skeleton:
         return R, ok
 
     def start(self, R0, k=0):
-        self.ct.syncs += 1
+        self.ct.syncs += muscle_syncs(self.muscle, self.s)
         Q, R, T, ok = intra_ortho(R0, self.muscle)
         if k in self.force_steps:
             ok = False
@@ -118,7 +119,7 @@ class BMGS(_Skeleton):
                 H[self.blk(i), self.blk(k)] = self.ip(self.V[i - 1], W)
                 W = W - self.V[i - 1] @ H[self.blk(i), self.blk(k)]
             self.ct.v_apps += 2
-            self.ct.syncs += 1
+            self.ct.syncs += muscle_syncs(self.muscle, self.s)
             Q, R, _, ok = intra_ortho(W, self.muscle)
             if k in self.force_steps:
                 ok = False
@@ -172,8 +173,8 @@ class BCGS_PIO(_Skeleton):
     columns."""
 
     def run(self, R0):
-        if self.muscle == "global":
-            raise ValueError("BCGS-PIO is defined for the classical paradigm only")
+        if self.muscle not in ("cholqr", "houseqr"):
+            raise ValueError("BCGS-PIO is built here with the CholQR and HouseQR muscles only")
         V1, self.Beta, _, ok = self.start(R0)
         if not ok:
             self.flagged, self.last = True, 0

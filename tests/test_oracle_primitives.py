@@ -112,3 +112,48 @@ def test_intra_ortho_t_factor_is_identity():
         assert ok and np.array_equal(T, np.eye(4))
     with pytest.raises(ValueError):
         oracle.intra_ortho(X, "tsqr")
+
+
+@pytest.mark.parametrize("muscle", ["mgs_svl", "mgs_lts"])
+def test_mgs_lowsync_muscles(muscle):
+    """Column-wise MGS-SVL / MGS-LTS (Sec. 5 muscles): X = Q R with R upper
+    triangular, positive diagonal, equal to the unique Householder R with
+    diag(R) > 0 on a well-conditioned block; T is unit upper triangular and
+    encodes the computed loss of orthogonality: SVL T^{-1} = I + triu(Q^T Q, 1),
+    LTS T = I + triu(Q^T Q, 1) (the Schreiber-Van Loan and lower-triangular-
+    solve representations)."""
+    from oracle.primitives import houseqr, intra_ortho
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((400, 6))
+    # a few nearly dependent columns make the loss of orthogonality visible
+    X[:, 4] = X[:, 1] + 1e-6 * rng.standard_normal(400)
+    Q, R, T, ok = intra_ortho(X, muscle)
+    assert ok
+    assert np.linalg.norm(Q @ R - X) <= 1e-13 * np.linalg.norm(X)
+    assert np.allclose(np.tril(R, -1), 0.0) and np.all(np.diag(R) > 0)
+    U = np.triu(Q.T @ Q, 1)
+    assert np.allclose(np.tril(T, -1), 0.0) and np.allclose(np.diag(T), 1.0)
+    if muscle == "mgs_svl":
+        assert np.linalg.norm(np.linalg.inv(T) - (np.eye(6) + U)) <= 1e-12
+    else:
+        assert np.linalg.norm(T - (np.eye(6) + U)) <= 1e-12
+    # well-conditioned block: the unique QR (Householder with diag(R) > 0)
+    Y = rng.standard_normal((300, 5))
+    Qm, Rm, Tm, okm = intra_ortho(Y, muscle)
+    Qh, Rh, okh = houseqr(Y)
+    assert okm and okh
+    assert np.linalg.norm(Rm - Rh) <= 1e-12 * np.linalg.norm(Rh)
+    assert np.linalg.norm(Qm - Qh) <= 1e-12
+    assert np.linalg.norm(Tm - np.eye(5)) <= 1e-13
+
+
+def test_mgs_muscle_flags_a_zero_column():
+    """A zero column leaves w = 0 exactly: w^T w is not positive, so the
+    muscle raises the flag (as CholQR does for the same block)."""
+    from oracle.primitives import intra_ortho
+    X = np.zeros((50, 3))
+    X[:, 0] = 1.0
+    X[:, 1] = np.arange(50.0)
+    for muscle in ("mgs_svl", "mgs_lts"):
+        _, _, _, ok = intra_ortho(X, muscle)
+        assert not ok
