@@ -81,7 +81,17 @@ typedef enum {
    Table 1): every block inner product is (1/s) trace(X^T Y) I_s and the
    muscle is the global scaling ||X||_F / sqrt(s) I_s (the paper forces that
    muscle in the global paradigm).  Not available with LSBA_BCGS_PIO. */
-typedef enum { LSBA_CHOLQR = 0, LSBA_HOUSEQR = 1, LSBA_GLOBAL = 2 } lsba_muscle;
+/* LSBA_MGS_SVL / LSBA_MGS_LTS are the column-wise low-sync MGS muscles
+   (Sec. 5; the column versions of Alg. 5, 3 s - 2 syncs per call), the
+   muscles the paper pairs with BMGS-SVL / BMGS-LTS; they also serve the
+   cycle start of every other skeleton but BCGS-PIO. */
+typedef enum {
+  LSBA_CHOLQR = 0,
+  LSBA_HOUSEQR = 1,
+  LSBA_GLOBAL = 2,
+  LSBA_MGS_SVL = 3,
+  LSBA_MGS_LTS = 4
+} lsba_muscle;
 
 typedef enum {
   LSBA_FP64 = 0,              /* every step in FP64                                        */

@@ -979,7 +979,7 @@ __global__ __launch_bounds__(NT) void small_svl_y_kernel(Dense d, int k) {
   if (d.skel == LSBA_BMGS_LTS) {
     double* X = fit ? lds + ks * s : d.scratch + (int64_t)ks * s;
     fwd_unit(d.Tt, ld, Yl, s, X, k, s, fit ? lds + 2 * ks * s : nullptr,
-             fit ? LDS_DBL - 2 * ks * s : 0);
+             fit ? LDS_DBL - 2 * ks * s : 0, d.mgs != 0);
     copy(ks, s, X, s, Hc, ld);
   } else {
     for (int w = threadIdx.x; w < ks * s; w += NT) {
@@ -1028,8 +1028,10 @@ __global__ __launch_bounds__(NT) void small_svl_io_kernel(Dense d, int k, int fo
   publish_coef(d);
 }
 
-// Alg. 5, after Z = V_{1:k}^T V_{k+1}: T_{1:k,k+1} = -T Z (SVL) or Z (LTS)
-// (T_{k+1,k+1} = I from CholQR).  Column k is then final (small_finalize).
+// Alg. 5, after Z = V_{1:k}^T V_{k+1}: T_{1:k,k+1} = -T Z T_{k+1,k+1} (SVL)
+// or Z T_{k+1,k+1} (LTS), with T_{k+1,k+1} the muscle's factor (I for
+// CholQR / HouseQR, unit upper triangular for the MGS muscles).  Column k is
+// then final (small_finalize).
 __global__ __launch_bounds__(NT) void small_svl_z_kernel(Dense d, int k) {
   __shared__ double lds[LDS_DBL];
   Ctl* ctl = d.ctl;
@@ -1045,6 +1047,21 @@ __global__ __launch_bounds__(NT) void small_svl_z_kernel(Dense d, int k) {
     copy(ks, s, Zl, s, Tc, ld);
   else
     rowprod_any(ks, s, ks, d.T, ld, 0, Zl, s, -1.0, nullptr, 0, Tc, ld);
+  if (d.mgs) {
+    // times T_{k+1,k+1} (unit upper triangular): column c of a row takes
+    // sum_{t <= c} row[t] T_{k+1,k+1}[t][c]; one thread per row of Tc
+    bar();
+    const double* Tkk = d.T + (int64_t)ks * ld + ks;
+    for (int a = threadIdx.x; a < ks; a += NT) {
+      double* row = Tc + (int64_t)a * ld;
+      for (int c = s - 1; c >= 1; --c) {
+        double acc = row[c];
+        for (int t = 0; t < c; ++t) acc = fma(row[t], Tkk[(int64_t)t * ld + c], acc);
+        row[c] = acc;
+      }
+    }
+  }
+  bar();
   for (int e = threadIdx.x; e < ks * s; e += NT) {
     const int i = e / s, c = e % s;
     d.Tt[(int64_t)(ks + c) * ld + i] = Tc[(int64_t)i * ld + c];
@@ -1189,6 +1206,149 @@ __global__ __launch_bounds__(NT) void small_pio_kernel(Dense d, int k, int force
   publish_coef(d);
 }
 
+// Column-wise MGS-SVL / MGS-LTS muscle (Sec. 5; the column version of
+// Alg. 5), one phase per launch; the host runs the column loop, each sync a
+// Gram product of the block being orthonormalized with itself (its column j
+// gives the inner products of column j with the earlier ones), each change
+// of the block an in-place update with the coefficients set here.  The
+// muscle's R and T live in P and J (unused by the skeletons while a muscle
+// runs).  For column j: PROJ h = T^T y (SVL) or T^{-T} y (LTS) from
+// y = Q_{1:j-1}^T x_j and x_j -= Q h; NORM r = sqrt(w^T w) (flag when not
+// positive finite) and x_j /= r; Z: T_{1:j-1,j} = -T z (SVL) or z (LTS).
+// FINISH places R and T: the cycle start (Beta, g = Beta C, the control
+// word, T_{1,1} for Alg. 5), Alg. 5's IntraOrtho (H_{k+1,k}, T_{k+1,k+1}) or
+// Alg. 2's (H_{k+1,k}).
+__device__ void mgs_flag(Ctl* ctl, int mode, int k) {
+  if (mode == MGS_START) {
+    ctl->status = ST_FLAGGED;
+    ctl->flag_step = 0;
+    ctl->last_valid = 0;
+    ctl->stop = 1;
+  } else {
+    raise_flag(ctl, k, k - 1);
+  }
+}
+
+__global__ __launch_bounds__(NT) void small_mgs_kernel(Dense d, int phase, int j, int mode, int k,
+                                                      int force) {
+  __shared__ double lds[2 * kMaxS * kMaxS];
+  Ctl* ctl = d.ctl;
+  const int s = d.s, ss = s * s, ld = d.ldh;
+  CoefLayout lay{s, d.mmax + 1};
+  double* Rm = d.P;
+  double* Tm = d.J;
+  double* coef = d.coef64;
+  const bool lts = d.mgs == 2;
+  if (phase == MGS_INIT) {
+    if (mode == MGS_START) {
+      if (threadIdx.x == 0) {
+        ctl->j = 0;
+        ctl->flag_step = -1;
+        ctl->last_valid = 1 << 30;
+        ctl->status = ST_RUNNING;
+        ctl->stop = 0;
+      }
+    } else if (ctl->stop) {
+      return;
+    }
+    for (int e = threadIdx.x; e < ss; e += NT) {
+      const double id = (e / s == e % s) ? 1.0 : 0.0;
+      Rm[e] = 0.0;
+      Tm[e] = id;
+      coef[lay.C1() + e] = id;
+      coef[lay.C2() + e] = id;
+    }
+    bar();
+    publish_coef(d);
+    return;
+  }
+  if (ctl->stop) return;
+  const double* G = d.G2;
+  if (phase == MGS_PROJ) {
+    double* h = lds;
+    if (threadIdx.x == 0) {
+      for (int i = 0; i < j; ++i) {
+        double acc;
+        if (lts) {   // T^T unit lower triangular: forward substitution
+          acc = G[i * s + j];
+          for (int t = 0; t < i; ++t) acc = fma(-Tm[t * s + i], h[t], acc);
+        } else {     // (T^T y)_i = sum_{t <= i} T[t][i] y_t
+          acc = 0.0;
+          for (int t = 0; t <= i; ++t) acc = fma(Tm[t * s + i], G[t * s + j], acc);
+        }
+        h[i] = acc;
+      }
+    }
+    bar();
+    for (int e = threadIdx.x; e < ss; e += NT) {
+      const int r = e / s, c = e % s;
+      coef[lay.C1() + e] = (c == j && r < j) ? -h[r] : (r == c ? 1.0 : 0.0);
+      if (c == j && r < j) Rm[e] = h[r];
+    }
+    bar();
+    publish_coef(d);
+    return;
+  }
+  if (phase == MGS_NORM) {
+    const double rr = G[j * s + j];
+    if (!(rr > 0.0) || !isfinite(rr)) {
+      if (threadIdx.x == 0) mgs_flag(ctl, mode, k);
+      return;
+    }
+    const double r = sqrt(rr);
+    for (int e = threadIdx.x; e < ss; e += NT) {
+      const int a = e / s, c = e % s;
+      coef[lay.C1() + e] = a == c ? (a == j ? 1.0 / r : 1.0) : 0.0;
+    }
+    if (threadIdx.x == 0) Rm[j * s + j] = r;
+    bar();
+    publish_coef(d);
+    return;
+  }
+  if (phase == MGS_Z) {
+    for (int i = threadIdx.x; i < j; i += NT) {
+      if (lts) {
+        Tm[i * s + j] = G[i * s + j];
+      } else {
+        double acc = 0.0;
+        for (int t = i; t < j; ++t) acc = fma(Tm[i * s + t], G[t * s + j], acc);
+        Tm[i * s + j] = -acc;
+      }
+    }
+    return;
+  }
+  // MGS_FINISH
+  if (force) {
+    if (threadIdx.x == 0) mgs_flag(ctl, mode, k);
+    return;
+  }
+  double* R = lds;
+  double* Ri = lds + ss;
+  for (int e = threadIdx.x; e < ss; e += NT) R[e] = Rm[e];
+  bar();
+  tri_inv_up(R, s, Ri);
+  for (int e = threadIdx.x; e < ss; e += NT) d.Rinv[e] = Ri[e];
+  const bool put_t = d.skel == LSBA_BMGS_SVL || d.skel == LSBA_BMGS_LTS;
+  if (mode == MGS_START) {
+    for (int e = threadIdx.x; e < ss; e += NT) d.Beta[e] = R[e];
+    for (int e = threadIdx.x; e < (d.mmax + 1) * ss; e += NT) d.g[e] = 0.0;
+    bar();
+    mm(s, s, s, 1.0, R, s, false, d.C, s, false, 0.0, d.g, s);
+  } else {
+    double* Hsub = d.H + (int64_t)(k * s) * ld + (k - 1) * s;
+    for (int e = threadIdx.x; e < ss; e += NT) Hsub[(int64_t)(e / s) * ld + (e % s)] = R[e];
+  }
+  if (put_t && mode != MGS_IOB) {
+    const int o = mode == MGS_START ? 0 : k * s;
+    for (int e = threadIdx.x; e < ss; e += NT) {
+      const int a = e / s, c = e % s;
+      d.T[(int64_t)(o + a) * ld + o + c] = Tm[e];
+      d.Tt[(int64_t)(o + c) * ld + o + a] = Tm[e];
+    }
+  }
+  bar();
+}
+
 // Alg. 2 (BMGS), loop step k, inner step i (both 1-based): H_{i,k} = V_i^T W
 // (the Gram output) and the coefficients of W <- W - V_i H_{i,k}.
 __global__ __launch_bounds__(NT) void small_bmgs_kernel(Dense d, int k, int i) {
@@ -1274,6 +1434,15 @@ void launch_small_pio(hipStream_t st, const Dense& d, int k, int force_flag, int
     SMALL_LAUNCH(small_pio_kernel<true><<<1, NT, 0, st>>>(d, k, force_flag, house));
   else
     SMALL_LAUNCH(small_pio_kernel<false><<<1, NT, 0, st>>>(d, k, force_flag, house));
+}
+void launch_small_mgs(hipStream_t st, const Dense& d, int phase, int j, int mode, int k,
+                      int force_flag, KTimer* tm) {
+  SMALL_LAUNCH(small_mgs_kernel<<<1, NT, 0, st>>>(d, phase, j, mode, k, force_flag));
+}
+void launch_t_identity(hipStream_t st, const Dense& d, KTimer* tm) {
+  const int64_t tot = (int64_t)d.ldh * d.ldh;
+  const int blocks = (int)std::min<int64_t>((tot + NT - 1) / NT, 1024);
+  SMALL_LAUNCH(t_identity_kernel<<<blocks, NT, 0, st>>>(d));
 }
 void launch_small_bmgs(hipStream_t st, const Dense& d, int k, int i, KTimer* tm) {
   SMALL_LAUNCH(small_bmgs_kernel<<<1, NT, 0, st>>>(d, k, i));

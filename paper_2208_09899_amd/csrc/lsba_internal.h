@@ -61,7 +61,7 @@ struct Dense {
   int method;     // lsba_method
   int mixed;      // 1: shifted-Cholesky fallback allowed (mixed form)
   int glob;       // 1: global block paradigm (every Gram block -> (1/s) tr I_s)
-  int pad0;       // keeps the struct free of padding bytes (always 0)
+  int mgs;        // column-wise muscle: 0 none, 1 MGS-SVL, 2 MGS-LTS
   double* H;      // block Hessenberg, (mmax + 2) s rows x ldh
   double* T;      // auxiliary T of Algs. 5 / 6, ldh x ldh
   double* Tt;     // its transpose (kept so that products read rows), ldh x ldh
@@ -245,6 +245,13 @@ void launch_small_pip(hipStream_t st, const Dense& d, int k, int force_flag,
 // H_{k+1,k} (flags) and the projection coefficients.
 void launch_small_pio(hipStream_t st, const Dense& d, int k, int force_flag, int house,
                       KTimer* tm = nullptr);
+// Column-wise MGS-SVL / MGS-LTS muscle, one phase per launch (the host runs
+// the column loop between Gram products and in-place block updates).
+enum MgsPhase : int { MGS_INIT = 0, MGS_PROJ = 1, MGS_NORM = 2, MGS_Z = 3, MGS_FINISH = 4 };
+enum MgsMode : int { MGS_START = 0, MGS_IO5 = 1, MGS_IOB = 2 };
+void launch_small_mgs(hipStream_t st, const Dense& d, int phase, int j, int mode, int k,
+                      int force_flag, KTimer* tm = nullptr);
+void launch_t_identity(hipStream_t st, const Dense& d, KTimer* tm = nullptr);
 // Alg. 2 (BMGS), loop step k, inner step i: H_{i,k} = V_i^T W and the
 // coefficients of W <- W - V_i H_{i,k}.
 void launch_small_bmgs(hipStream_t st, const Dense& d, int k, int i, KTimer* tm = nullptr);

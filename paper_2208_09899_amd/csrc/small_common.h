@@ -778,7 +778,7 @@ __device__ __forceinline__ void rowprod_any(int M, int s, int K, const double* A
 // b = 0..k-1.  Row blocks of L are staged in LDS (`buf`, cap doubles) in
 // chunks, so that each chunk costs one memory latency.  X: k s x s, ld s.
 __device__ __forceinline__ void fwd_unit(const double* Lt, int ld, const double* Rhs, int ldr, double* X, int k,
-                         int s, double* buf, int cap) {
+                         int s, double* buf, int cap, bool diag = false) {
   const int ss = s * s;
   int b = 0;
   while (b < k) {
@@ -818,6 +818,21 @@ __device__ __forceinline__ void fwd_unit(const double* Lt, int ld, const double*
         const double* Lrow = staged ? buf + off : Lt + (int64_t)(c * s) * ld;
         const int ldl = staged ? w : ld;
         mm(s, s, w, -1.0, Lrow, ldl, false, X, s, false, 1.0, X + (int64_t)c * ss, s);
+      }
+      if (diag) {
+        // a unit lower triangular (not identity) diagonal block: row by row
+        bar();
+        double* Xc = X + (int64_t)c * ss;
+        const double* Ld = Lt + (int64_t)(c * s) * ld + c * s;
+        for (int i = 1; i < s; ++i) {
+          if (threadIdx.x < s) {
+            const int col = threadIdx.x;
+            double acc = Xc[i * s + col];
+            for (int t = 0; t < i; ++t) acc = fma(-Ld[(int64_t)i * ld + t], Xc[t * s + col], acc);
+            Xc[i * s + col] = acc;
+          }
+          bar();
+        }
       }
       off += s * w;
     }

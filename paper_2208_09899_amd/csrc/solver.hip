@@ -208,11 +208,13 @@ struct EventTimer final : KTimer {
 
 // Counts of one cycle as the paper counts them (Sec. 5): A-calls, basis
 // applications and syncs of the loop steps the algorithm executed.
-void cycle_counts(int skel, int j, int status, int flag_step, int64_t& a, int64_t& v,
+// `ms` is the muscle's syncs per IntraOrtho call (1, or 3 s - 2 for the
+// column-wise MGS muscles).
+void cycle_counts(int skel, int ms, int j, int status, int flag_step, int64_t& a, int64_t& v,
                   int64_t& sy) {
   const bool delayed = skel == LSBA_BCGSI_LS || skel == LSBA_BMGS_CWY || skel == LSBA_BMGS_ICWY;
   const bool bcgs = skel == LSBA_BCGSI_LS;
-  sy += 1;   // IntraOrtho of the starting block
+  sy += ms;   // IntraOrtho of the starting block
   if (status == ST_FLAGGED && flag_step == 0) return;
   int full, partial = 0;
   if (status == ST_FLAGGED) {
@@ -242,7 +244,7 @@ void cycle_counts(int skel, int j, int status, int flag_step, int64_t& a, int64_
     // step k: one A-call, k block inner products and the IntraOrtho
     for (int k = 1; k <= full + partial; ++k) {
       a += 1;
-      sy += k + 1;
+      sy += k + ms;
       v += 2;
     }
     return;
@@ -259,12 +261,13 @@ void cycle_counts(int skel, int j, int status, int flag_step, int64_t& a, int64_
       v += 2;
     }
   } else {
+    // Alg. 5 step: Y, the IntraOrtho, Z; a flagged step stops after the IntraOrtho
     a += full;
-    sy += 3 * full;
+    sy += (2 + ms) * full;
     v += 3 * full;
     if (partial) {
       a += 1;
-      sy += 2;
+      sy += 1 + ms;
       v += 2;
     }
   }
@@ -449,7 +452,7 @@ Krylov<T> make_krylov_with(Alloc&& alloc, int64_t n, int s, int m, const lsba_pa
   d.ldh = ldh;
   d.skel = p.skeleton;
   d.glob = p.muscle == LSBA_GLOBAL ? 1 : 0;
-  d.pad0 = 0;
+  d.mgs = p.muscle == LSBA_MGS_SVL ? 1 : (p.muscle == LSBA_MGS_LTS ? 2 : 0);
   d.method = p.method;
   d.mixed = sizeof(T) == sizeof(float) ? 1 : 0;
   d.gstride = per_step ? (long long)gslot : 0;
@@ -729,6 +732,35 @@ struct CycleRunner {
     };
     nev = 0;
     const int fk = (p.force_flag_cycle == cyc_) ? p.force_flag_step : -1;
+    const bool mgs = p.muscle == LSBA_MGS_SVL || p.muscle == LSBA_MGS_LTS;
+    // the column-wise muscle on `src` into `dst` (in place when equal): per
+    // column j, the syncs are Gram products of the block with itself and the
+    // changes in-place updates with the coefficients the phase kernel sets
+    auto mgs_muscle = [&](int mode, const T* src, T* dst, int kk, int force) {
+      launch_small_mgs(st, d, MGS_INIT, 0, mode, kk, 0, tm);
+      auto apply = [&](const T* from) {
+        UpdateArgs<T> u = upd_args(k);
+        u.in1 = from;
+        u.out1 = dst;
+        launch_update<T>(st, u, ctl, true, tm);
+      };
+      if (src != dst) apply(src);
+      for (int j = 0; j < s; ++j) {
+        if (j > 0) {
+          launch_gram<T>(st, gram_args<T>(k, 0, {dst}, {dst}), k.partial, d.G2, ctl, tm);
+          launch_small_mgs(st, d, MGS_PROJ, j, mode, kk, 0, tm);
+          apply(dst);
+        }
+        launch_gram<T>(st, gram_args<T>(k, 0, {dst}, {dst}), k.partial, d.G2, ctl, tm);
+        launch_small_mgs(st, d, MGS_NORM, j, mode, kk, 0, tm);
+        apply(dst);
+        if (j > 0) {
+          launch_gram<T>(st, gram_args<T>(k, 0, {dst}, {dst}), k.partial, d.G2, ctl, tm);
+          launch_small_mgs(st, d, MGS_Z, j, mode, kk, 0, tm);
+        }
+      }
+      launch_small_mgs(st, d, MGS_FINISH, 0, mode, kk, force, tm);
+    };
     // IntraOrtho(R0) by CholQR: V_1 = R0 B^{-1} (and U = V_1 for the delayed skeletons)
     tag(0, 0);
     if (p.muscle == LSBA_HOUSEQR) {
@@ -736,6 +768,16 @@ struct CycleRunner {
       launch_house<T>(st, d, n, s, R0, slot(k, 0), delayed ? k.U : (T*)nullptr, k.hwork,
                       HM_START, 0, fk == 0 ? 1 : 0, tm);
       tag(0, 1);
+    } else if (mgs) {
+      if (skel_uses_t(d.skel)) launch_t_identity(st, d, tm);
+      mgs_muscle(MGS_START, R0, slot(k, 0), 0, fk == 0 ? 1 : 0);
+      tag(0, 1);
+      if (delayed) {   // U = V_1 (the muscle left C2 = I)
+        UpdateArgs<T> u = upd_args(k);
+        u.in2 = slot(k, 0);
+        u.out2 = k.U;
+        launch_update<T>(st, u, ctl, true, tm);
+      }
     } else {
       launch_gram<T>(st, gram_args<T>(k, 0, {R0}, {R0}), k.partial, d.G, ctl, tm);
       launch_small_start(st, d, fk == 0 ? 1 : 0, tm);
@@ -872,6 +914,9 @@ struct CycleRunner {
           launch_house<T>(st, d, n, s, k.W, slot(k, kk), (T*)nullptr, k.hwork, HM_IO, kk, force,
                           tm);
           tag(kk, 1);
+        } else if (mgs) {
+          mgs_muscle(MGS_IOB, k.W, slot(k, kk), kk, force);
+          tag(kk, 1);
         } else {
           launch_gram<T>(st, gram_args<T>(k, 0, {k.W}, {k.W}), k.partial, d.G2, ctl, tm);
           launch_small_svl_io(st, d, kk, force, tm);
@@ -907,6 +952,10 @@ struct CycleRunner {
           // IntraOrtho of the projected block in place; H_{kk+1,kk} = R
           launch_house<T>(st, d, n, s, slot(k, kk), slot(k, kk), (T*)nullptr, k.hwork, HM_IO, kk,
                           force, tm);
+          tag(kk, 1);
+        } else if (mgs) {
+          // column-wise muscle in place; H_{kk+1,kk} = R, T_{kk+1,kk+1} = its T
+          mgs_muscle(MGS_IO5, slot(k, kk), slot(k, kk), kk, force);
           tag(kk, 1);
         } else {
           launch_gram<T>(st, gram_args<T>(k, 0, {slot(k, kk)}, {slot(k, kk)}), k.partial, d.G2,
@@ -977,7 +1026,8 @@ struct CycleRunner {
         tm->kill_after(hc.flag_step, true);
       tm->flush();
     }
-    cycle_counts(p.skeleton, j, cst, hc.flag_step, out.a, out.v, out.sy);
+    const int ms = (p.muscle == LSBA_MGS_SVL || p.muscle == LSBA_MGS_LTS) ? 3 * kp->s - 2 : 1;
+    cycle_counts(p.skeleton, ms, j, cst, hc.flag_step, out.a, out.v, out.sy);
     for (int i = 0; i < j; ++i) res->res.push_back(c->hist_host[i]);
     if (rec_loo) {
       for (int i = 0; i < j; ++i) {
@@ -1135,10 +1185,9 @@ void validate_params(const lsba_params* p, int s) {
   if (p->m < 1 || p->m > kMaxM) throw ArgError{"m must be in [1, 128]"};
   if (p->method != LSBA_FOM && p->method != LSBA_GMRES) throw ArgError{"bad method"};
   if (p->skeleton < LSBA_BCGSI_LS || p->skeleton > LSBA_BCGS_PIO) throw ArgError{"bad skeleton"};
-  if (p->muscle != LSBA_CHOLQR && p->muscle != LSBA_HOUSEQR && p->muscle != LSBA_GLOBAL)
-    throw ArgError{"bad muscle"};
-  if (p->muscle == LSBA_GLOBAL && p->skeleton == LSBA_BCGS_PIO)
-    throw ArgError{"BCGS-PIO is defined for the classical paradigm only"};
+  if (p->muscle < LSBA_CHOLQR || p->muscle > LSBA_MGS_LTS) throw ArgError{"bad muscle"};
+  if (p->skeleton == LSBA_BCGS_PIO && p->muscle != LSBA_CHOLQR && p->muscle != LSBA_HOUSEQR)
+    throw ArgError{"BCGS-PIO is built with the CholQR and HouseQR muscles only"};
   if (p->precision != LSBA_FP64 && p->precision != LSBA_MIXED) throw ArgError{"bad precision"};
   if (!(p->tol >= 0.0)) throw ArgError{"tol must be >= 0"};
   if (p->max_cycles < 1) throw ArgError{"max_cycles must be >= 1"};

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "liblsba.so")
 METHODS = {"fom": 0, "gmres": 1}
 SKELETONS = {"bcgsi_ls": 0, "bmgs_svl": 1, "bmgs_lts": 2, "bmgs_cwy": 3, "bmgs_icwy": 4,
              "bcgs_pip": 5, "bmgs": 6, "bcgs_pio": 7}
-MUSCLES = {"cholqr": 0, "houseqr": 1, "global": 2}
+MUSCLES = {"cholqr": 0, "houseqr": 1, "global": 2, "mgs_svl": 3, "mgs_lts": 4}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 REC_LOO, REC_TRUE_RES = 1, 2
 

@@ -96,6 +96,46 @@ def test_global_paradigm_convdiff_ragged(skel, s):
     assert_parity(g, o)
 
 
+MGS_PAIRS = [("bmgs_svl", "mgs_svl"), ("bmgs_lts", "mgs_lts"), ("bmgs", "mgs_svl"),
+             ("bcgsi_ls", "mgs_lts"), ("bmgs_cwy", "mgs_svl")]
+
+
+@pytest.mark.parametrize("method", ["fom", "gmres"])
+@pytest.mark.parametrize("skel,muscle", MGS_PAIRS)
+def test_mgs_muscles_laplace2d_32(method, skel, muscle):
+    """The column-wise MGS-SVL / MGS-LTS muscles (Sec. 5) against the
+    oracle's: with their own skeletons (every IntraOrtho), with BMGS, and at
+    the cycle start of the one-muscle-call skeletons."""
+    wl = w.workload("laplace2d", 32)
+    g = gpu_solve(wl.A, wl.B, method=method, skeleton=skel, muscle=muscle, m=30, tol=1e-8,
+                  max_cycles=1000)
+    o = oracle_solve(wl.A, wl.B, method, skel, m=30, tol=1e-8, max_cycles=1000, muscle=muscle)
+    assert_parity(g, o)
+
+
+@pytest.mark.parametrize("skel,muscle", [("bmgs_svl", "mgs_svl"), ("bmgs_lts", "mgs_lts")])
+@pytest.mark.parametrize("s", [1, 3, 8, 16])
+def test_mgs_muscles_convdiff_ragged(skel, muscle, s):
+    A = w.convdiff_2d(45, 3.0, 0.7)
+    B = w.rhs(A.n, s, seed=41 + s)
+    g = gpu_solve(A, B, method="gmres", skeleton=skel, muscle=muscle, m=12, tol=1e-9,
+                  max_cycles=300)
+    o = oracle_solve(A, B, "gmres", skel, m=12, tol=1e-9, max_cycles=300, muscle=muscle)
+    assert_parity(g, o)
+
+
+@pytest.mark.parametrize("skel,muscle", [("bmgs_svl", "mgs_svl"), ("bmgs", "mgs_lts")])
+def test_mgs_muscle_forced_flag_matches(skel, muscle):
+    A = w.convdiff_2d(30, 2.0, 0.3)
+    B = w.rhs(A.n, 4, seed=5)
+    g = gpu_solve(A, B, method="gmres", skeleton=skel, muscle=muscle, m=10, tol=1e-10,
+                  max_cycles=200, force_flag=(1, 6))
+    o = oracle_solve(A, B, "gmres", skel, m=10, tol=1e-10, max_cycles=200, force_flag=(1, 6),
+                     muscle=muscle)
+    assert_parity(g, o)
+    assert g.m_after[0] < 10
+
+
 def test_global_paradigm_rejected_for_pio():
     A = w.laplace_1d(50)
     B = w.rhs(50, 2, 1)
@@ -178,9 +218,14 @@ def test_paper_tridiag_counts_on_gpu():
                  "gl-bmgs_icwy": (621, gl, (630, 1872, 639)),
                  "gl-bcgs_pip": (621, gl, (621, 1863, 630))}
     expect.update(expect_gl)
+    # the column-wise muscles the paper pairs with BMGS-SVL / BMGS-LTS (3 s - 2
+    # syncs per muscle call): 96 iterations, [70, 26]
+    expect.update({"mgs-bmgs_svl": (96, [70, 26], (96, 288, 584)),
+                   "mgs-bmgs_lts": (96, [70, 26], (96, 288, 584))})
     for name, (iters, cycles, counts) in expect.items():
-        skel = name[3:] if name.startswith("gl-") else name
-        mu = "global" if name.startswith("gl-") else "cholqr"
+        skel = name.split("-", 1)[1] if name.startswith(("gl-", "mgs-")) else name
+        mu = ("global" if name.startswith("gl-") else
+              ("mgs_" + skel[5:] if name.startswith("mgs-") else "cholqr"))
         g = gpu_solve(A, B, method="fom", skeleton=skel, muscle=mu, m=70, tol=0.0,
                       max_cycles=10, max_iters=iters)
         o = oracle_solve(A, B, "fom", skel, m=70, tol=0.0, max_cycles=10, max_iters=iters,
