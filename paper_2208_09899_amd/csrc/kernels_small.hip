@@ -282,8 +282,43 @@ __global__ __launch_bounds__(NT) void small_core_kernel(Dense d, int k, int m, i
     Gp = Gk;
   }
   // [Omega | P~ - Y^T Z] = G(r0.., :) - Y^T [Y Z]
-  mm_t<true, false>(s, ldg, r0, -1.0, Gp, ldg, Gp, ldg, 0.0, OmP, ldg, Gp + (int64_t)r0 * ldg,
-                    ldg);
+  if constexpr (FIT) {
+    mm_t<true, false>(s, ldg, r0, -1.0, Gp, ldg, Gp, ldg, 0.0, OmP, ldg, Gp + (int64_t)r0 * ldg,
+                      ldg);
+  } else {
+    // the Gram output stays in global memory: stream its rows through LDS in
+    // chunks (contiguous loads), each thread accumulating its outputs (i, j)
+    // of Y^T [Y Z] in a fixed row order
+    double* chunk = lds + lused;
+    const int crow = (LDS_DBL - lused) / ldg < 64 ? (LDS_DBL - lused) / ldg : 64;
+    constexpr int OPT = (kMaxS * 2 * kMaxS + NT - 1) / NT;   // outputs per thread, at most
+    double acc[OPT];
+#pragma unroll
+    for (int u = 0; u < OPT; ++u) acc[u] = 0.0;
+    const int nout = s * ldg;
+    for (int t0 = 0; t0 < r0; t0 += crow) {
+      const int nr = r0 - t0 < crow ? r0 - t0 : crow;
+      bar();
+      bcopy(Gp + (int64_t)t0 * ldg, chunk, nr * ldg);
+      bar();
+#pragma unroll
+      for (int u = 0; u < OPT; ++u) {
+        const int e = threadIdx.x + u * NT;
+        if (e < nout) {
+          const int i = e / ldg, j = e % ldg;
+          double a = acc[u];
+          for (int t = 0; t < nr; ++t) a = fma(chunk[t * ldg + i], chunk[t * ldg + j], a);
+          acc[u] = a;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < OPT; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (e < nout) OmP[e] = Gp[(int64_t)r0 * ldg + e] - acc[u];
+    }
+    bar();
+  }
   bool ok = chol_flag(d, OmP, ldg, R, dinv);
   if (force) ok = false;
   if (!ok) {
@@ -296,9 +331,9 @@ __global__ __launch_bounds__(NT) void small_core_kernel(Dense d, int k, int m, i
   for (int e = threadIdx.x; e < ss; e += NT) {
     coef[lay.C1() + e] = Ri[e];
     d.H[(int64_t)(r0 + e / s) * ld + (k - 2) * s + (e % s)] = R[e];
+    d.RiS[(int64_t)k * ss + e] = Ri[e];
     if (!last) {
       coef[lay.C2() + e] = Ri[e];
-      d.RiS[(int64_t)k * ss + e] = Ri[e];
       const int i = e / s, c = e % s;
       double acc = 0.0;
 #pragma unroll 8
@@ -330,9 +365,45 @@ __global__ __launch_bounds__(NT) void small_core_kernel(Dense d, int k, int m, i
     }
   }
   bar();
-  // one pass over the rows of [Y Z]: A = -Y R^{-1}, B = -Z R^{-1} and the
-  // folded B + A D = -Z R^{-1} + Y W
-  for (int e = threadIdx.x; e < r0 * s; e += NT) {
+  // the s x s coefficients for the precision form's update (the row blocks
+  // A, B, BF follow in small_core_rows_kernel, which writes both copies)
+  if (d.mixed) {
+    float* fc = (float*)d.coefT;
+    for (int e = threadIdx.x; e < ss; e += NT) {
+      fc[lay.C1() + e] = (float)coef[lay.C1() + e];
+      if (!last) {
+        fc[lay.C2() + e] = (float)coef[lay.C2() + e];
+        fc[lay.D() + e] = (float)coef[lay.D() + e];
+        fc[lay.C1D() + e] = (float)coef[lay.C1D() + e];
+      }
+    }
+  }
+}
+
+// Alg. 7 core step, second part (after small_core_kernel, k >= 2): one pass
+// over the rows of [Y Z], spread over the chip: A = -Y R^{-1},
+// B = -Z R^{-1} and the folded B + A D = -Z R^{-1} + Y W, with R^{-1} and
+// W = R^{-1} P R^{-1} as the core step left them (its R^{-1} slot and the
+// C1 D coefficient, -W).  Each entry is written in FP64 and, for the
+// precision form, in FP32.
+__global__ __launch_bounds__(NT) void small_core_rows_kernel(Dense d, int k, int m) {
+  __shared__ double Ri[kMaxS * kMaxS], Wl[kMaxS * kMaxS];
+  Ctl* ctl = d.ctl;
+  if (ctl->stop) return;
+  const int s = d.s, ss = s * s;
+  CoefLayout lay{s, d.mmax + 1};
+  const bool last = (k == m + 1);
+  const int ldg = last ? s : 2 * s;
+  const int r0 = (k - 1) * s;
+  const double* Gp = d.G + (int64_t)k * d.gstride;
+  double* coef = d.coef64;
+  for (int e = threadIdx.x; e < ss; e += NT) {
+    Ri[e] = d.RiS[(int64_t)k * ss + e];
+    Wl[e] = last ? 0.0 : -coef[lay.C1D() + e];
+  }
+  bar();
+  float* fc = d.mixed ? (float*)d.coefT : nullptr;
+  for (int e = blockIdx.x * NT + threadIdx.x; e < r0 * s; e += gridDim.x * NT) {
     const int i = e / s, c = e % s;
     const double* y = Gp + (int64_t)i * ldg;
     double a = 0.0, b = 0.0, f = 0.0;
@@ -343,17 +414,20 @@ __global__ __launch_bounds__(NT) void small_core_kernel(Dense d, int k, int m, i
       if (!last) {
         const double zt = y[s + t];
         b = fma(zt, Ri[t * s + c], b);
-        f = fma(yt, R[t * s + c], f);
+        f = fma(yt, Wl[t * s + c], f);
       }
     }
     coef[lay.A(0) + e] = -a;
+    if (fc) fc[lay.A(0) + e] = (float)(-a);
     if (!last) {
       coef[lay.B(0) + e] = -b;
       coef[lay.BF(0) + e] = f - b;
+      if (fc) {
+        fc[lay.B(0) + e] = (float)(-b);
+        fc[lay.BF(0) + e] = (float)(f - b);
+      }
     }
   }
-  bar();
-  publish_coef(d);
 }
 
 // LDS layout of small_cwy (Alg. 6, 2 <= k <= m): small matrices, Y R^{-1},
@@ -1407,6 +1481,9 @@ void launch_small_delayed(hipStream_t st, const Dense& d, int k, int m, int forc
       SMALL_LAUNCH(small_core_kernel<true><<<1, NT, 0, st>>>(d, k, m, force_flag));
     else
       SMALL_LAUNCH(small_core_kernel<false><<<1, NT, 0, st>>>(d, k, m, force_flag));
+    const int rows = (k - 1) * s * s;
+    const int blocks = std::min((rows + NT - 1) / NT, 128);
+    SMALL_LAUNCH(small_core_rows_kernel<<<blocks, NT, 0, st>>>(d, k, m));
   }
   else
     SMALL_LAUNCH(small_delayed_kernel<<<1, NT, 0, st>>>(d, k, m, force_flag));
