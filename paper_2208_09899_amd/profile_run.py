@@ -29,7 +29,7 @@ if __package__ in (None, ""):
 # kernel class: (kernel-name substrings, source file)
 KERNEL_CLASSES = {"update": (("update_kernel", "update_mfma"), "kernels_update.hip"),
                   "gram": (("gram_stage1", "gram_mfma"), "kernels_gram.hip"),
-                  "spmm": (("spmm_kernel",), "kernels_sparse.hip")}
+                  "spmm": (("spmm_kernel", "spmm_coop_kernel"), "kernels_sparse.hip")}
 
 
 def _counter_means(path, counter):
