@@ -14,6 +14,8 @@ Modules:
   skeletons  -- block Arnoldi skeletons (Algs. 2, 3, 5, 6, 7)
   solver     -- restarted BFOM / BGMRES driver with cospatial restarts and
                 the adaptive restart heuristic (Secs. 2.4.1, 2.4.2, 4)
+  precond    -- ILU(0) factors and their application, right preconditioning
+                (Sec. 5, the tests on matrices from applications)
 
 Every public function cites the passage of the paper it follows.  Readings
 taken where the paper is silent or ambiguous are listed in the docstrings
@@ -22,6 +24,8 @@ of the functions that make them.
 from .primitives import ip, chol_flag, cholqr, houseqr, intra_ortho
 from .skeletons import SKELETONS, make_skeleton
 from .solver import solve, OracleResult, small_solve
+from .precond import ilu0, ilu0_apply, ZeroPivot
 
 __all__ = ["ip", "chol_flag", "cholqr", "houseqr", "intra_ortho", "SKELETONS",
-           "make_skeleton", "solve", "OracleResult", "small_solve"]
+           "make_skeleton", "solve", "OracleResult", "small_solve", "ilu0", "ilu0_apply",
+           "ZeroPivot"]

@@ -37,6 +37,7 @@ import dataclasses
 
 import numpy as np
 
+from .precond import RightPreconditioned
 from .skeletons import Counters, make_skeleton
 
 
@@ -92,7 +93,7 @@ def small_solve(method: str, Hj1: np.ndarray, BC: np.ndarray, s: int):
 def solve(A, B, method: str = "gmres", skeleton: str = "bcgsi_ls", muscle: str = "cholqr",
           m: int = 20, tol: float = 1e-8, max_cycles: int = 50, record_loo: bool = False,
           force_flag=(), keep_cycles: bool = False, max_iters: int | None = None,
-          x_star=None) -> OracleResult:
+          x_star=None, precond=None) -> OracleResult:
     """Restarted block solve of A X = B (Secs. 2.4, 4).
 
     Stopping: by default after the first column whose residual estimate
@@ -105,7 +106,25 @@ def solve(A, B, method: str = "gmres", skeleton: str = "bcgsi_ls", muscle: str =
     ``force_flag`` is a collection of (cycle, step) pairs (1-based cycle,
     skeleton loop step k; k = 0 is the cycle's first IntraOrtho) at which the
     Cholesky breakdown flag is raised regardless of the data -- a test hook for
-    the adaptive-restart path."""
+    the adaptive-restart path.
+
+    ``precond`` (optional) is a pair (L, U) of ILU(0) factors
+    (``oracle.precond.ilu0``): the cycles then run on A M^{-1}, M = L U
+    (right preconditioning), and the returned X is M^{-1} Y for the Krylov
+    solution Y; the per-cycle data kept by ``keep_cycles`` stays in terms
+    of Y."""
+    if precond is not None:
+        Aop = RightPreconditioned(A, *precond)
+        res = _solve(Aop, B, method, skeleton, muscle, m, tol, max_cycles, record_loo,
+                     force_flag, keep_cycles, max_iters, x_star, Aop.solution)
+        res.X = Aop.solution(res.X)
+        return res
+    return _solve(A, B, method, skeleton, muscle, m, tol, max_cycles, record_loo, force_flag,
+                  keep_cycles, max_iters, x_star, lambda Y: Y)
+
+
+def _solve(A, B, method, skeleton, muscle, m, tol, max_cycles, record_loo, force_flag,
+           keep_cycles, max_iters, x_star, sol) -> OracleResult:
     B = np.asarray(B, dtype=np.float64)
     n, s = B.shape
     X = np.zeros((n, s))
@@ -137,7 +156,7 @@ def solve(A, B, method: str = "gmres", skeleton: str = "bcgsi_ls", muscle: str =
             elif Xi is None:
                 crit = np.inf
             else:
-                crit = np.linalg.norm(X + sk.Vcat(j) @ Xi - x_star) / np.linalg.norm(x_star)
+                crit = np.linalg.norm(sol(X + sk.Vcat(j) @ Xi) - x_star) / np.linalg.norm(x_star)
             if crit <= tol:
                 conv = True
                 break
