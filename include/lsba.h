@@ -20,6 +20,9 @@
  *   - adaptive restarting on a Cholesky breakdown ......... Sec. 4
  *   - loss of orthogonality ||I - V^T V||_2 ............... Sec. 2.3, eq. loo
  *   - counts of A-calls, basis applications, syncs ........ Sec. 2.1, Sec. 5
+ *   - ILU(0) right preconditioning ........................ Sec. 5 (tests on
+ *                                                           matrices from
+ *                                                           applications)
  *
  * Real double-precision arithmetic (the conjugate transpose of the paper is
  * the plain transpose).  Every step of the solve runs in the library's own
@@ -158,13 +161,15 @@ typedef enum {
   LSBA_K_GRAM_REDUCE = 2,     /* Gram products, fixed-order reduction stage (0 bytes)        */
   LSBA_K_UPDATE = 3,          /* fused block updates / projections / basis applications      */
   LSBA_K_SMALL = 4,           /* small dense steps (0 bytes)                                 */
-  LSBA_K_RESIDUAL = 5         /* FP64 true residual B - A X                                  */
+  LSBA_K_RESIDUAL = 5,        /* FP64 true residual B - A X                                  */
+  LSBA_K_PRECOND = 6          /* ILU(0) triangular sweeps (one launch per level or run of
+                                 chained levels)                                             */
 } lsba_kernel_kind;
 /* Time the kernel classes whose bits (1u << lsba_kernel_kind) are set in
  * kind_mask (LSBA_TIME_ALL: every class; 0: timing off).  Launches of other
  * classes are not bracketed by events, so timing one class perturbs the run
  * least.  Either way the statistics are cleared. */
-#define LSBA_TIME_ALL 0x3Fu
+#define LSBA_TIME_ALL 0x7Fu
 lsba_status lsba_context_set_timing(lsba_context* ctx, uint32_t kind_mask);
 /* Launch count, summed device milliseconds and summed algorithmic bytes of a
  * kernel class since timing was enabled (all zero when disabled). */
@@ -205,6 +210,58 @@ void lsba_operator_destroy(lsba_operator* op);
 lsba_status lsba_solve(lsba_context* ctx, const lsba_operator* op, const lsba_params* prm,
                        int32_t s, const double* B, int64_t ldb, double* X, int64_t ldx,
                        int on_device, lsba_result** res);
+
+/* ---------------------------------------------------------------- ILU(0)
+ * Incomplete LU factorization with no fill (the preconditioner of the
+ * paper's tests on matrices from applications, Sec. 5): L unit lower
+ * triangular and U upper triangular on A's stored pattern with
+ * (L U)_ij = a_ij for every stored (i, j) -- Gaussian elimination in row
+ * order with every update outside the pattern dropped.  Rows and columns are
+ * used in the order given; explicit zeros count as stored entries.
+ * Factorization and every application run on the device, one dependency
+ * level of rows at a time (levels are computed on the host from the pattern
+ * once, at creation). */
+typedef struct lsba_precond lsba_precond;
+
+/* Factor op's matrix.  Every row must store its diagonal entry and no column
+ * twice (else LSBA_ERR_ARG); a zero or non-finite pivot u_ii is LSBA_ERR_ARG
+ * with the row in lsba_last_error.  The factors are device memory owned by
+ * the handle; op may be destroyed afterwards.  Destroying the context first
+ * releases the factors (lsba_precond_destroy then frees only the handle). */
+lsba_status lsba_precond_create_ilu0(lsba_context* ctx, const lsba_operator* op,
+                                     lsba_precond** pc);
+void lsba_precond_destroy(lsba_precond* pc);
+
+/* Z = M^{-1} Y = U^{-1} (L^{-1} Y) for an n x s block (1 <= s <= 32;
+ * row-major, leading dimensions ldy, ldz >= s; host or device per on_device;
+ * Z may equal Y).  Blocks until done. */
+lsba_status lsba_precond_apply(lsba_context* ctx, const lsba_precond* pc, int32_t s,
+                               const double* Y, int64_t ldy, double* Z, int64_t ldz,
+                               int on_device);
+
+/* Copy the factors to host arrays in CSR form on A's pattern with each row's
+ * columns ascending: row_ptr [n+1], col_idx [nnz], values [nnz]; entries left
+ * of the diagonal are L's multipliers (L's unit diagonal is not stored), the
+ * diagonal and the entries right of it are U. */
+lsba_status lsba_precond_factors(const lsba_precond* pc, int64_t* row_ptr, int32_t* col_idx,
+                                 double* values);
+
+/* Size, stored entries and number of dependency levels of the forward (L)
+ * and backward (U) sweeps; any output pointer may be NULL. */
+lsba_status lsba_precond_info(const lsba_precond* pc, int64_t* n, int64_t* nnz,
+                              int32_t* levels_lower, int32_t* levels_upper);
+
+/* lsba_solve with right preconditioning: the restart cycles run on A M^{-1}
+ * (each basis block goes through M^{-1} before the SpMM) and X = M^{-1} Y
+ * for the cycles' solution Y.  The residual of A M^{-1} Y = B is B - A X, so
+ * tol, the residual history and the true residual mean what they mean
+ * without M.  pc must come from ctx and have op's size (it may be the
+ * factorization of another matrix of that size).  FP64 form only
+ * (LSBA_MIXED: LSBA_ERR_UNSUPPORTED). */
+lsba_status lsba_solve_precond(lsba_context* ctx, const lsba_operator* op,
+                               const lsba_precond* pc, const lsba_params* prm, int32_t s,
+                               const double* B, int64_t ldb, double* X, int64_t ldx,
+                               int on_device, lsba_result** res);
 
 /* Variant of lsba_solve for callers that cannot allocate device memory
  * (tight serving loops, harnesses that forbid hipMalloc): it calls no

@@ -1,0 +1,362 @@
+// ILU(0) preconditioner: factorization and application, level-scheduled.
+//
+// The paper's tests on matrices from applications (Sec. 5) precondition with
+// an incomplete LU factorization with no fill.  ILU(0) keeps L (unit lower)
+// and U (upper) on A's pattern with (L U)_ij = a_ij there; it is Gaussian
+// elimination in row order with every update outside the pattern dropped.
+// Row i of the elimination reads rows k < i that it stores, and a triangular
+// sweep's row reads the rows its factor part stores; both therefore run one
+// dependency level at a time: the rows of a level are independent.
+//
+// Launch plan: a level whose rows (times the lanes per row) fill several
+// workgroups gets a launch of its own (the launch boundary orders it after
+// the previous level); runs of smaller levels are chained inside ONE
+// workgroup of 1024 threads with a workgroup barrier between levels, which
+// saves a launch per level where the graph's levels are narrow.  No kernel
+// waits on another workgroup.
+//
+// Sweep layout: positions in level order (rows of a level ascending), each
+// position's off-diagonal entries contiguous, so the lanes of a wavefront
+// read neighbouring rows' entries and the s lanes of a row read s contiguous
+// elements of each gathered row of the block.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+#include "lsba_internal.h"
+
+namespace lsba {
+
+namespace {
+
+constexpr int kIluChainThreads = 1024;   // workgroup of a chained run of levels
+constexpr int kIluChainPasses = 4;       // a level is chained if it fits this many passes
+constexpr int kIluThreads = 256;         // workgroup of a one-level launch
+constexpr int kIluMaxGrid = 1 << 16;
+
+// Factorization of the rows of levels [l0, l1) (one thread per row).  The
+// updates are evaluated as written (no fused multiply-add), the order of the
+// elimination: multipliers by ascending k, each followed by its row's
+// updates.
+__global__ __launch_bounds__(kIluChainThreads) void ilu_factor_kernel(
+    int l0, int l1, const int* __restrict__ lvl_ptr, const int* __restrict__ rows,
+    const int64_t* __restrict__ frp, const int* __restrict__ fci,
+    const int64_t* __restrict__ fdg, double* fv, unsigned long long* bad) {
+#pragma clang fp contract(off)
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int l = l0; l < l1; ++l) {
+    const int b = lvl_ptr[l], e = lvl_ptr[l + 1];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < e - b; t += stride) {
+      const int64_t i = rows[b + t];
+      const int64_t pe = frp[i + 1], di = fdg[i];
+      for (int64_t p = frp[i]; p < di; ++p) {
+        const int64_t k = fci[p];
+        const double lik = fv[p] / fv[fdg[k]];
+        fv[p] = lik;
+        // a_ij -= l_ik u_kj for the j > k that rows i and k both store
+        int64_t q = p + 1, r = fdg[k] + 1;
+        const int64_t re = frp[k + 1];
+        while (q < pe && r < re) {
+          const int cq = fci[q], cr = fci[r];
+          if (cq == cr) {
+            const double prod = lik * fv[r];
+            fv[q] = fv[q] - prod;
+            ++q;
+            ++r;
+          } else if (cq < cr) {
+            ++q;
+          } else {
+            ++r;
+          }
+        }
+      }
+      const double d = fv[di];
+      if (!(d != 0.0 && isfinite(d))) atomicMin(bad, (unsigned long long)i);
+    }
+    if (l + 1 < l1) __syncthreads();
+  }
+}
+
+// One sweep over levels [l0, l1): 2^lshift lanes per row, lane c < s owns
+// column c.  Forward (LOWER): z_i = y_i - sum_j l_ij z_j; backward:
+// x_i = (z_i - sum_j u_ij x_j) / u_ii.  Y and Z may be the same block.
+template <bool LOWER>
+__global__ __launch_bounds__(kIluChainThreads) void ilu_sweep_kernel(
+    int s, int lshift, int l0, int l1, const int* __restrict__ lvl_ptr,
+    const int* __restrict__ rows, const int64_t* __restrict__ rp, const int* __restrict__ ci,
+    const double* __restrict__ v, const double* __restrict__ piv, const double* Y, double* Z,
+    const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->stop) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int lmask = (1 << lshift) - 1;
+  for (int l = l0; l < l1; ++l) {
+    const int b = lvl_ptr[l], e = lvl_ptr[l + 1];
+    const int64_t total = (int64_t)(e - b) << lshift;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+      const int c = (int)(t & lmask);
+      if (c < s) {
+        const int k = b + (int)(t >> lshift);
+        const int64_t i = rows[k];
+        double acc = Y[i * s + c];
+        const int64_t pe = rp[k + 1];
+        for (int64_t p = rp[k]; p < pe; ++p) acc -= v[p] * Z[(int64_t)ci[p] * s + c];
+        if (!LOWER) acc = acc / piv[k];
+        Z[i * s + c] = acc;
+      }
+    }
+    if (l + 1 < l1) __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void ilu_gather_kernel(int64_t count,
+                                                         const int64_t* __restrict__ map,
+                                                         const double* __restrict__ src,
+                                                         double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[map[i]];
+}
+
+void gather(hipStream_t st, int64_t count, const int64_t* map, const double* src, double* dst) {
+  if (count <= 0) return;
+  const int64_t g = (count + 255) / 256;
+  ilu_gather_kernel<<<dim3((unsigned)g), dim3(256), 0, st>>>(count, map, src, dst);
+}
+
+// Launch plan of a sweep for 2^lshift lanes per row (see the file comment).
+std::vector<IluLaunch> make_plan(const std::vector<int>& hptr, const std::vector<int64_t>& ents,
+                                 int lshift) {
+  std::vector<IluLaunch> plan;
+  const int nlev = (int)hptr.size() - 1;
+  const int64_t chain_rows = ((int64_t)kIluChainThreads * kIluChainPasses) >> lshift;
+  int l = 0;
+  while (l < nlev) {
+    const int64_t r = hptr[l + 1] - hptr[l];
+    if (r > chain_rows) {
+      const int64_t thr = r << lshift;
+      const int64_t g = std::min<int64_t>((thr + kIluThreads - 1) / kIluThreads, kIluMaxGrid);
+      plan.push_back({l, l + 1, (int)g, r, ents[l + 1] - ents[l]});
+      ++l;
+    } else {
+      int l1 = l + 1;
+      while (l1 < nlev && hptr[l1 + 1] - hptr[l1] <= chain_rows) ++l1;
+      plan.push_back({l, l1, 1, (int64_t)hptr[l1] - hptr[l], ents[l1] - ents[l]});
+      l = l1;
+    }
+  }
+  return plan;
+}
+
+template <typename T>
+std::string dev_alloc(IluFactors& f, T** p, int64_t count) {
+  void* q = nullptr;
+  if (hipMalloc(&q, sizeof(T) * (size_t)std::max<int64_t>(count, 1)) != hipSuccess)
+    return "device allocation of the ILU(0) factors failed";
+  f.mem.push_back(q);
+  *p = (T*)q;
+  return "";
+}
+
+// Host analysis of one sweep: levels, level order, entries per position, and
+// the map from each entry to its position in the sorted factor array.
+struct SweepHost {
+  std::vector<int> ptr, rows;
+  std::vector<int64_t> rp, map, pivmap, lents;
+  std::vector<int> ci;
+};
+
+SweepHost analyse(int64_t n, const std::vector<int64_t>& srp, const std::vector<int>& sci,
+                  const std::vector<int64_t>& dg, bool lower) {
+  SweepHost h;
+  std::vector<int> lev(n, 0);
+  int nl = 0;
+  auto level_of = [&](int64_t i) {
+    int m = -1;
+    const int64_t a = lower ? srp[i] : dg[i] + 1, b = lower ? dg[i] : srp[i + 1];
+    for (int64_t p = a; p < b; ++p) m = std::max(m, lev[sci[p]]);
+    lev[i] = m + 1;
+    nl = std::max(nl, m + 2);
+  };
+  if (lower)
+    for (int64_t i = 0; i < n; ++i) level_of(i);
+  else
+    for (int64_t i = n - 1; i >= 0; --i) level_of(i);
+  h.ptr.assign(nl + 1, 0);
+  for (int64_t i = 0; i < n; ++i) h.ptr[lev[i] + 1] += 1;
+  for (int l = 0; l < nl; ++l) h.ptr[l + 1] += h.ptr[l];
+  std::vector<int> fill(h.ptr.begin(), h.ptr.end() - 1);
+  h.rows.resize(n);
+  for (int64_t i = 0; i < n; ++i) h.rows[fill[lev[i]]++] = (int)i;
+  h.rp.resize(n + 1);
+  h.rp[0] = 0;
+  h.pivmap.resize(lower ? 0 : n);
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t i = h.rows[k];
+    const int64_t a = lower ? srp[i] : dg[i] + 1, b = lower ? dg[i] : srp[i + 1];
+    for (int64_t p = a; p < b; ++p) {
+      h.ci.push_back(sci[p]);
+      h.map.push_back(p);
+    }
+    h.rp[k + 1] = h.rp[k] + (b - a);
+    if (!lower) h.pivmap[k] = dg[i];
+  }
+  h.lents.resize(nl + 1);
+  for (int l = 0; l <= nl; ++l) h.lents[l] = h.rp[h.ptr[l]];
+  return h;
+}
+
+// Copy one sweep's schedule to the device: its arrays are allocated into
+// `keep` (the factors), the entry maps of the set-up into `tmp`.
+std::string upload(hipStream_t st, IluFactors& keep, IluFactors& tmp, int64_t n, IluSweep& sw,
+                   const SweepHost& h, bool lower, int64_t** map_dev, int64_t** pivmap_dev) {
+  std::string e;
+  const int64_t ne = (int64_t)h.ci.size();
+  sw.nlev = (int)h.ptr.size() - 1;
+  if (!(e = dev_alloc(keep, &sw.lvl_ptr, sw.nlev + 1)).empty()) return e;
+  if (!(e = dev_alloc(keep, &sw.rows, n)).empty()) return e;
+  if (!(e = dev_alloc(keep, &sw.rp, n + 1)).empty()) return e;
+  if (!(e = dev_alloc(keep, &sw.ci, ne)).empty()) return e;
+  if (!(e = dev_alloc(keep, &sw.v, ne)).empty()) return e;
+  if (!(e = dev_alloc(tmp, map_dev, ne)).empty()) return e;
+  if (!lower) {
+    if (!(e = dev_alloc(keep, &sw.piv, n)).empty()) return e;
+    if (!(e = dev_alloc(tmp, pivmap_dev, n)).empty()) return e;
+  }
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    return bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess;
+  };
+  bool ok = cp(sw.lvl_ptr, h.ptr.data(), sizeof(int) * h.ptr.size()) &&
+            cp(sw.rows, h.rows.data(), sizeof(int) * n) &&
+            cp(sw.rp, h.rp.data(), sizeof(int64_t) * (n + 1)) &&
+            cp(sw.ci, h.ci.data(), sizeof(int) * ne) &&
+            cp(*map_dev, h.map.data(), sizeof(int64_t) * ne);
+  if (ok && !lower) ok = cp(*pivmap_dev, h.pivmap.data(), sizeof(int64_t) * n);
+  if (!ok) return "copy of the ILU(0) level schedule failed";
+  for (int j = 0; j < 6; ++j) sw.plan[j] = make_plan(h.ptr, h.lents, j);
+  return "";
+}
+
+int lanes_shift_of(int s) {
+  int sh = 0;
+  while ((1 << sh) < s) ++sh;
+  return sh;
+}
+
+template <bool LOWER>
+void launch_sweep(hipStream_t st, const IluSweep& sw, int s, const double* Y, double* Z,
+                  const Ctl* ctl, KTimer* tm) {
+  const int lsh = lanes_shift_of(s);
+  for (const IluLaunch& L : sw.plan[lsh]) {
+    // algorithmic bytes: the off-diagonal entries (value + column), the row
+    // list and entry offsets (+ pivots), one read of the input rows and one
+    // write of the output rows (the gathered rows are outputs of earlier
+    // levels, counted where they were written)
+    const double bytes = 12.0 * (double)L.ents + (LOWER ? 12.0 : 20.0) * (double)L.rows +
+                         16.0 * (double)L.rows * s;
+    const int block = L.grid == 1 ? kIluChainThreads : kIluThreads;
+    launch_k(tm, KK_PRECOND, bytes, ilu_sweep_kernel<LOWER>, dim3(L.grid), dim3(block), 0, st,
+             s, lsh, L.l0, L.l1, (const int*)sw.lvl_ptr, (const int*)sw.rows,
+             (const int64_t*)sw.rp, (const int*)sw.ci, (const double*)sw.v,
+             (const double*)sw.piv, Y, Z, ctl);
+  }
+}
+
+}  // namespace
+
+void ilu_free(IluFactors& f) {
+  for (void* p : f.mem) (void)hipFree(p);
+  f.mem.clear();
+  f.frp = nullptr;
+  f.fci = nullptr;
+  f.fv = nullptr;
+  f.lo = IluSweep{};
+  f.up = IluSweep{};
+}
+
+// On failure the caller releases f with ilu_free.
+std::string ilu_build(hipStream_t st, int64_t n, int64_t nnz, const int64_t* rp_h,
+                      const int* ci_h, const double* val_dev, IluFactors& f, int64_t* bad_row) {
+  *bad_row = -1;
+  f.n = n;
+  f.nnz = nnz;
+  // rows with sorted columns; perm maps a sorted position to A's position
+  std::vector<int64_t> srp(rp_h, rp_h + n + 1), perm(nnz), dg(n, -1);
+  std::vector<int> sci(nnz);
+  std::vector<std::pair<int, int64_t>> row;
+  for (int64_t i = 0; i < n; ++i) {
+    row.clear();
+    for (int64_t p = rp_h[i]; p < rp_h[i + 1]; ++p) row.push_back({ci_h[p], p});
+    std::sort(row.begin(), row.end());
+    for (size_t q = 0; q < row.size(); ++q) {
+      const int64_t p = rp_h[i] + (int64_t)q;
+      sci[p] = row[q].first;
+      perm[p] = row[q].second;
+      if (q > 0 && row[q].first == row[q - 1].first)
+        return "row " + std::to_string(i) + " stores column " + std::to_string(row[q].first) +
+               " twice";
+      if (row[q].first == i) dg[i] = p;
+    }
+    if (dg[i] < 0) return "row " + std::to_string(i) + " stores no diagonal entry";
+  }
+  const SweepHost lo = analyse(n, srp, sci, dg, true);
+  const SweepHost up = analyse(n, srp, sci, dg, false);
+  f.nnz_lo = (int64_t)lo.ci.size();
+  f.nnz_up = (int64_t)up.ci.size();
+  std::string e;
+  int64_t *perm_d = nullptr, *dg_d = nullptr, *lmap = nullptr, *umap = nullptr,
+          *pmap = nullptr, *unused = nullptr;
+  unsigned long long* bad_d = nullptr;
+  if (!(e = dev_alloc(f, &f.frp, n + 1)).empty()) return e;
+  if (!(e = dev_alloc(f, &f.fci, nnz)).empty()) return e;
+  if (!(e = dev_alloc(f, &f.fv, nnz)).empty()) return e;
+  // set-up only arrays, freed at the end
+  IluFactors tmp;
+  auto fail_tmp = [&](const std::string& m) {
+    (void)hipStreamSynchronize(st);
+    ilu_free(tmp);
+    return m;
+  };
+  if (!(e = dev_alloc(tmp, &perm_d, nnz)).empty()) return fail_tmp(e);
+  if (!(e = dev_alloc(tmp, &dg_d, n)).empty()) return fail_tmp(e);
+  if (!(e = dev_alloc(tmp, &bad_d, 1)).empty()) return fail_tmp(e);
+  const unsigned long long none = ULLONG_MAX;
+  if (hipMemcpyAsync(f.frp, srp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      (nnz && hipMemcpyAsync(f.fci, sci.data(), sizeof(int) * nnz, hipMemcpyHostToDevice, st) !=
+                  hipSuccess) ||
+      (nnz && hipMemcpyAsync(perm_d, perm.data(), sizeof(int64_t) * nnz, hipMemcpyHostToDevice,
+                             st) != hipSuccess) ||
+      hipMemcpyAsync(dg_d, dg.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(bad_d, &none, sizeof(none), hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail_tmp("copy of the ILU(0) pattern failed");
+  if (!(e = upload(st, f, tmp, n, f.lo, lo, true, &lmap, &unused)).empty()) return fail_tmp(e);
+  if (!(e = upload(st, f, tmp, n, f.up, up, false, &umap, &pmap)).empty()) return fail_tmp(e);
+  gather(st, nnz, perm_d, val_dev, f.fv);
+  for (const IluLaunch& L : f.lo.plan[0]) {
+    const int block = L.grid == 1 ? kIluChainThreads : kIluThreads;
+    ilu_factor_kernel<<<dim3(L.grid), dim3(block), 0, st>>>(
+        L.l0, L.l1, f.lo.lvl_ptr, f.lo.rows, f.frp, f.fci, dg_d, f.fv, bad_d);
+  }
+  gather(st, f.nnz_lo, lmap, f.fv, f.lo.v);
+  gather(st, f.nnz_up, umap, f.fv, f.up.v);
+  gather(st, n, pmap, f.fv, f.up.piv);
+  unsigned long long bad = none;
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&bad, bad_d, sizeof(bad), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail_tmp("ILU(0) factorization kernels failed");
+  ilu_free(tmp);
+  if (bad != none) {
+    *bad_row = (int64_t)bad;
+    return "zero or non-finite pivot in row " + std::to_string(bad);
+  }
+  return "";
+}
+
+void launch_ilu_apply(hipStream_t st, const IluFactors& f, int s, const double* Y, double* Z,
+                      const Ctl* ctl, KTimer* tm) {
+  launch_sweep<true>(st, f.lo, s, Y, Z, ctl, tm);
+  launch_sweep<false>(st, f.up, s, Z, Z, ctl, tm);
+}
+
+}  // namespace lsba

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
+#include <vector>
 
 #include "lsba.h"
 
@@ -115,7 +117,7 @@ struct CoefLayout {
 // Kernel classes for the device-time statistics (values of lsba_kernel_kind).
 enum KernelKind : int {
   KK_SPMM = 0, KK_GRAM = 1, KK_GRAM_REDUCE = 2, KK_UPDATE = 3, KK_SMALL = 4, KK_RESIDUAL = 5,
-  KK_COUNT = 6
+  KK_PRECOND = 6, KK_COUNT = 7
 };
 
 // Optional launch timer: begin()/end() bracket one kernel launch of class
@@ -273,6 +275,51 @@ size_t house_work_doubles(int64_t n, int s);
 template <typename T>
 void launch_house(hipStream_t st, const Dense& d, int64_t n, int s, const T* X, T* out1, T* out2,
                   double* work, int mode, int k, int force, KTimer* tm = nullptr);
+
+// ------------------------------------------------------------ ILU(0)
+// One triangular sweep of the ILU(0) factors in level order: rows of one
+// level depend only on rows of earlier levels, so a level's rows are solved
+// in parallel.  Position k (0 <= k < n) of the level order holds row rows[k];
+// the positions of level l are [lvl_ptr[l], lvl_ptr[l+1]).  The off-diagonal
+// entries of position k (strictly lower part for the forward sweep, strictly
+// upper part for the backward sweep) are ci/v[rp[k] .. rp[k+1]), columns
+// ascending; piv[k] is u_ii (backward sweep only).
+struct IluLaunch {
+  int l0, l1;       // levels [l0, l1) of one launch
+  int grid;         // workgroups (1: the levels are chained in one workgroup)
+  int64_t rows, ents;   // rows and off-diagonal entries the launch covers
+};
+struct IluSweep {
+  int nlev = 0;
+  int* lvl_ptr = nullptr;
+  int* rows = nullptr;
+  int64_t* rp = nullptr;
+  int* ci = nullptr;
+  double* v = nullptr;
+  double* piv = nullptr;
+  std::vector<IluLaunch> plan[6];   // launches for 2^j lanes per row, j = 0..5
+};
+// ILU(0) factors of a CSR matrix: the factors on A's pattern with each row's
+// columns sorted (fv: strictly lower part = L's multipliers, the rest = U),
+// natural row order, plus both sweeps in level order.
+struct IluFactors {
+  int64_t n = 0, nnz = 0, nnz_lo = 0, nnz_up = 0;
+  int64_t* frp = nullptr;
+  int* fci = nullptr;
+  double* fv = nullptr;
+  IluSweep lo, up;
+  std::vector<void*> mem;   // every device allocation of the factors
+};
+// Analyse the pattern (host copies of A's row pointer and column indices),
+// then factor A's values (device) on st.  Returns "" on success, else the
+// reason (missing diagonal, duplicate column, allocation or HIP failure;
+// for a zero or non-finite pivot *bad_row receives its row, else -1).
+std::string ilu_build(hipStream_t st, int64_t n, int64_t nnz, const int64_t* rp_h,
+                      const int* ci_h, const double* val_dev, IluFactors& f, int64_t* bad_row);
+void ilu_free(IluFactors& f);
+// Z = U^{-1} L^{-1} Y for n x s row-major blocks (Z may alias Y).
+void launch_ilu_apply(hipStream_t st, const IluFactors& f, int s, const double* Y, double* Z,
+                      const Ctl* ctl, KTimer* tm = nullptr);
 
 // v rotated right by N lanes within each row of 16 lanes (DPP row_ror):
 // lane 16 r + i receives the value of lane 16 r + ((i - N) mod 16).

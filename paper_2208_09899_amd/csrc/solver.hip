@@ -27,6 +27,7 @@
 #include <set>
 #include <string>
 #include <type_traits>
+#include <type_traits>
 #include <vector>
 
 #include "lsba_internal.h"
@@ -81,6 +82,7 @@ struct lsba_context {
   // device memory and detaches them, so that a later lsba_operator_destroy
   // (in any order, e.g. from a garbage collector) never reads a freed context
   std::set<lsba_operator*> ops;
+  std::set<lsba_precond*> pcs;   // live preconditioners, released likewise
 };
 
 
@@ -91,6 +93,13 @@ struct lsba_operator {
   int* ci = nullptr;
   double* val = nullptr;
   float* val32 = nullptr;
+};
+
+// Right ILU(0) preconditioner of an operator (factors in device memory).
+struct lsba_precond {
+  lsba_context* ctx = nullptr;
+  const lsba_operator* op = nullptr;
+  IluFactors f;
 };
 
 struct lsba_result {
@@ -547,6 +556,21 @@ struct CycleRunner {
   int m = 0, cyc = 0;
   CycleOut out;
   UpdateArgs<T> uapply{};
+  // right preconditioning (FP64 only): the cycle's operator is A M^{-1},
+  // applied as W = A (M^{-1} V) with M^{-1} V in zpc
+  const IluFactors* pc = nullptr;
+  double* zpc = nullptr;
+
+  // W = A X, or A M^{-1} X with a preconditioner
+  void op_apply(hipStream_t st, const T* X, T* W, const Ctl* ctl, EventTimer* tm) {
+    if constexpr (std::is_same_v<T, double>) {
+      if (pc) {
+        launch_ilu_apply(st, *pc, kp->s, X, zpc, ctl, tm);
+        X = zpc;
+      }
+    }
+    launch_spmm<T>(st, kp->n, op->nnz, kp->s, op->rp, op->ci, val, X, W, ctl, tm);
+  }
 
   void begin() {
     Krylov<T>& k = *kp;
@@ -597,7 +621,7 @@ struct CycleRunner {
     const int fk = (p.force_flag_cycle == cyc_) ? p.force_flag_step : -1;
     const int64_t ints[] = {(int64_t)sizeof(T), op->n, op->nnz, m, fk, p.muscle, p.skeleton,
                             p.method, rec_loo ? 1 : 0};
-    const void* ptrs[] = {op->rp, op->ci, val, R0, x, c->side, c->side2};
+    const void* ptrs[] = {op->rp, op->ci, val, R0, x, c->side, c->side2, pc, zpc};
     put(ints, sizeof(ints));
     put(ptrs, sizeof(ptrs));
     put(kp, sizeof(Krylov<T>));
@@ -800,7 +824,7 @@ struct CycleRunner {
         const int force = fk == kk ? 1 : 0;
         const bool last = kk == m + 1;
         tag(kk, 0);
-        if (!last) launch_spmm<T>(st, n, op->nnz, s, op->rp, op->ci, val, k.U, k.W, ctl, tm);
+        if (!last) op_apply(st, k.U, k.W, ctl, tm);
         if (kk == 1)
           launch_gram<T>(st, gram_args<T>(k, 1, {}, {k.W}), k.partial, gslot(kk), ctl, tm);
         else if (!last)
@@ -846,7 +870,7 @@ struct CycleRunner {
       for (int kk = 1; kk <= m; ++kk) {
         const int force = fk == kk ? 1 : 0;
         tag(kk, 0);
-        launch_spmm<T>(st, n, op->nnz, s, op->rp, op->ci, val, slot(k, kk - 1), k.W, ctl, tm);
+        op_apply(st, slot(k, kk - 1), k.W, ctl, tm);
         launch_gram<T>(st, gram_args<T>(k, kk, {k.W}, {k.W}), k.partial, d.G, ctl, tm);
         launch_small_pip(st, d, kk, force, tm);
         tag(kk, 1);
@@ -870,7 +894,7 @@ struct CycleRunner {
       for (int kk = 1; kk <= m; ++kk) {
         const int force = fk == kk ? 1 : 0;
         tag(kk, 0);
-        launch_spmm<T>(st, n, op->nnz, s, op->rp, op->ci, val, slot(k, kk - 1), k.W, ctl, tm);
+        op_apply(st, slot(k, kk - 1), k.W, ctl, tm);
         launch_gram<T>(st, gram_args<T>(k, kk, {}, {k.W}), k.partial, d.G, ctl, tm);
         const int house = p.muscle == LSBA_HOUSEQR ? 1 : 0;
         if (house)
@@ -898,7 +922,7 @@ struct CycleRunner {
       for (int kk = 1; kk <= m; ++kk) {
         const int force = fk == kk ? 1 : 0;
         tag(kk, 0);
-        launch_spmm<T>(st, n, op->nnz, s, op->rp, op->ci, val, slot(k, kk - 1), k.W, ctl, tm);
+        op_apply(st, slot(k, kk - 1), k.W, ctl, tm);
         for (int i = 1; i <= kk; ++i) {
           launch_gram<T>(st, gram_args<T>(k, 0, {slot(k, i - 1)}, {k.W}), k.partial, d.G, ctl,
                          tm);
@@ -937,7 +961,7 @@ struct CycleRunner {
       for (int kk = 1; kk <= m; ++kk) {
         const int force = fk == kk ? 1 : 0;
         tag(kk, 0);
-        launch_spmm<T>(st, n, op->nnz, s, op->rp, op->ci, val, slot(k, kk - 1), k.W, ctl, tm);
+        op_apply(st, slot(k, kk - 1), k.W, ctl, tm);
         launch_gram<T>(st, gram_args<T>(k, kk, {}, {k.W}), k.partial, d.G, ctl, tm);
         launch_small_svl_y(st, d, kk, tm);
         {
@@ -1054,8 +1078,10 @@ struct CycleRunner {
 template <typename T>
 CycleOut run_cycles(lsba_context* c, const lsba_operator* op, const lsba_params& p,
                     Krylov<T>& k, const T* val, const T* rhs, T* x, double nB, double tol,
-                    lsba_result* res) {
+                    lsba_result* res, const IluFactors* pc = nullptr, double* zpc = nullptr) {
   CycleRunner<T> r{c, op, p, &k, val, rhs, x, nB, tol, res};
+  r.pc = pc;
+  r.zpc = zpc;
   r.begin();
   for (;;) {
     if (r.cyc >= p.max_cycles) {
@@ -1489,6 +1515,11 @@ void lsba_context_destroy(lsba_context* c) {
     op->ctx = nullptr;   // detached: lsba_operator_destroy then frees only the handle
   }
   c->ops.clear();
+  for (lsba_precond* pc : c->pcs) {
+    ilu_free(pc->f);
+    pc->ctx = nullptr;   // detached likewise
+  }
+  c->pcs.clear();
   ctx_release(c);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->ctl_host) (void)hipHostFree(c->ctl_host);
@@ -1600,9 +1631,9 @@ void lsba_operator_destroy(lsba_operator* op) {
   delete op;
 }
 
-lsba_status lsba_solve(lsba_context* c, const lsba_operator* op, const lsba_params* prm,
-                       int32_t s, const double* B, int64_t ldb, double* X, int64_t ldx,
-                       int on_device, lsba_result** out) {
+static lsba_status solve_impl(lsba_context* c, const lsba_operator* op, const lsba_precond* pc,
+                              const lsba_params* prm, int32_t s, const double* B, int64_t ldb,
+                              double* X, int64_t ldx, int on_device, lsba_result** out) {
   if (!c) return fail(nullptr, LSBA_ERR_ARG, "context is NULL");
   if (!op || !B || !X || !out) return fail(c, LSBA_ERR_ARG, "NULL pointer argument");
   if (op->ctx != c) return fail(c, LSBA_ERR_ARG, "operator belongs to another context");
@@ -1610,6 +1641,12 @@ lsba_status lsba_solve(lsba_context* c, const lsba_operator* op, const lsba_para
   try {
     validate_params(prm, s);
     if (ldb < s || ldx < s) throw ArgError{"ldb and ldx must be >= s"};
+    if (pc) {
+      if (pc->ctx != c) throw ArgError{"preconditioner belongs to another context"};
+      if (pc->f.n != op->n) throw ArgError{"preconditioner and operator differ in size"};
+      if (prm->precision != LSBA_FP64)
+        throw Unsupported{"preconditioning is available in the FP64 form only"};
+    }
   } catch (const ArgError& e) {
     return fail(c, LSBA_ERR_ARG, e.msg);
   } catch (const Unsupported& e) {
@@ -1638,7 +1675,12 @@ lsba_status lsba_solve(lsba_context* c, const lsba_operator* op, const lsba_para
       r->true_relres = 0.0;
     } else if (p.precision == LSBA_FP64) {
       Krylov<double> k = make_krylov<double>(c, n, s, p.m, p, "d_");
-      CycleOut o = run_cycles<double>(c, op, p, k, op->val, B64, X64, nB, p.tol, r);
+      double* zpc = pc ? (double*)ctx_buf(c, "Zpc", blk64) : nullptr;
+      CycleOut o = run_cycles<double>(c, op, p, k, op->val, B64, X64, nB, p.tol, r,
+                                      pc ? &pc->f : nullptr, zpc);
+      // right preconditioning: the cycles accumulate Y of A M^{-1} Y = B;
+      // X = M^{-1} Y
+      if (pc) launch_ilu_apply(st, pc->f, s, X64, X64, nullptr, c->timer);
       r->status = o.status;
       r->iters = o.iters;
       r->a = o.a;
@@ -1699,6 +1741,131 @@ lsba_status lsba_solve(lsba_context* c, const lsba_operator* op, const lsba_para
   }
   *out = r;
   return r->status;
+}
+
+lsba_status lsba_solve(lsba_context* c, const lsba_operator* op, const lsba_params* prm,
+                       int32_t s, const double* B, int64_t ldb, double* X, int64_t ldx,
+                       int on_device, lsba_result** out) {
+  return solve_impl(c, op, nullptr, prm, s, B, ldb, X, ldx, on_device, out);
+}
+
+lsba_status lsba_solve_precond(lsba_context* c, const lsba_operator* op, const lsba_precond* pc,
+                               const lsba_params* prm, int32_t s, const double* B, int64_t ldb,
+                               double* X, int64_t ldx, int on_device, lsba_result** out) {
+  if (c && !pc) return fail(c, LSBA_ERR_ARG, "NULL preconditioner");
+  return solve_impl(c, op, pc, prm, s, B, ldb, X, ldx, on_device, out);
+}
+
+// ------------------------------------------------------------ ILU(0)
+
+static void precond_release(lsba_precond* pc) {
+  if (pc->ctx) {
+    (void)hipSetDevice(pc->ctx->device);
+    if (pc->ctx->stream) (void)hipStreamSynchronize(pc->ctx->stream);
+  }
+  ilu_free(pc->f);
+}
+
+lsba_status lsba_precond_create_ilu0(lsba_context* c, const lsba_operator* op,
+                                     lsba_precond** out) {
+  if (!c) return fail(nullptr, LSBA_ERR_ARG, "context is NULL");
+  if (!op || !out) return fail(c, LSBA_ERR_ARG, "NULL pointer argument");
+  if (op->ctx != c) return fail(c, LSBA_ERR_ARG, "operator belongs to another context");
+  *out = nullptr;
+  auto* pc = new (std::nothrow) lsba_precond();
+  if (!pc) return fail(c, LSBA_ERR_OOM, "host allocation failed");
+  pc->ctx = c;
+  pc->op = op;
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    std::vector<int64_t> rp(op->n + 1);
+    std::vector<int> ci(op->nnz);
+    HIPCHK(hipMemcpy(rp.data(), op->rp, sizeof(int64_t) * (op->n + 1), hipMemcpyDeviceToHost));
+    if (op->nnz)
+      HIPCHK(hipMemcpy(ci.data(), op->ci, sizeof(int) * op->nnz, hipMemcpyDeviceToHost));
+    int64_t bad = -1;
+    const std::string e =
+        ilu_build(c->stream, op->n, op->nnz, rp.data(), ci.data(), op->val, pc->f, &bad);
+    if (!e.empty()) {
+      precond_release(pc);
+      delete pc;
+      const bool arg = bad >= 0 || e.find("row ") == 0;
+      return fail(c, arg ? LSBA_ERR_ARG : LSBA_ERR_HIP, e);
+    }
+  } catch (const HipError& e) {
+    precond_release(pc);
+    delete pc;
+    return fail(c, LSBA_ERR_HIP, e.msg);
+  }
+  c->pcs.insert(pc);
+  *out = pc;
+  return LSBA_OK;
+}
+
+void lsba_precond_destroy(lsba_precond* pc) {
+  if (!pc) return;
+  precond_release(pc);
+  if (pc->ctx) pc->ctx->pcs.erase(pc);
+  delete pc;
+}
+
+lsba_status lsba_precond_apply(lsba_context* c, const lsba_precond* pc, int32_t s,
+                               const double* Y, int64_t ldy, double* Z, int64_t ldz,
+                               int on_device) {
+  if (!c) return fail(nullptr, LSBA_ERR_ARG, "context is NULL");
+  if (!pc || !Y || !Z) return fail(c, LSBA_ERR_ARG, "NULL pointer argument");
+  if (pc->ctx != c) return fail(c, LSBA_ERR_ARG, "preconditioner belongs to another context");
+  if (s < 1 || s > kMaxS) return fail(c, LSBA_ERR_ARG, "s must be in [1, 32]");
+  if (ldy < s || ldz < s) return fail(c, LSBA_ERR_ARG, "ldy and ldz must be >= s");
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    const int64_t n = pc->f.n;
+    const hipMemcpyKind in_kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const hipMemcpyKind out_kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    double* W = (double*)ctx_buf(c, "PcW", (size_t)n * s * sizeof(double));
+    HIPCHK(hipMemcpy2DAsync(W, s * sizeof(double), Y, ldy * sizeof(double), s * sizeof(double),
+                            n, in_kind, st));
+    launch_ilu_apply(st, pc->f, s, W, W, nullptr, c->timer);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy2DAsync(Z, ldz * sizeof(double), W, s * sizeof(double), s * sizeof(double),
+                            n, out_kind, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (c->timer) c->timer->flush();
+  } catch (const HipError& e) {
+    return fail(c, LSBA_ERR_HIP, e.msg);
+  }
+  return LSBA_OK;
+}
+
+lsba_status lsba_precond_factors(const lsba_precond* pc, int64_t* row_ptr, int32_t* col_idx,
+                                 double* values) {
+  if (!pc || !row_ptr || (pc->f.nnz > 0 && (!col_idx || !values))) return LSBA_ERR_ARG;
+  if (!pc->ctx) return LSBA_ERR_ARG;
+  lsba_context* c = pc->ctx;
+  try {
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int64_t n = pc->f.n, nnz = pc->f.nnz;
+    HIPCHK(hipMemcpy(row_ptr, pc->f.frp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+    if (nnz) {
+      HIPCHK(hipMemcpy(col_idx, pc->f.fci, sizeof(int) * nnz, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(values, pc->f.fv, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+    }
+  } catch (const HipError& e) {
+    return fail(c, LSBA_ERR_HIP, e.msg);
+  }
+  return LSBA_OK;
+}
+
+lsba_status lsba_precond_info(const lsba_precond* pc, int64_t* n, int64_t* nnz,
+                              int32_t* levels_lower, int32_t* levels_upper) {
+  if (!pc) return LSBA_ERR_ARG;
+  if (n) *n = pc->f.n;
+  if (nnz) *nnz = pc->f.nnz;
+  if (levels_lower) *levels_lower = pc->f.lo.nlev;
+  if (levels_upper) *levels_upper = pc->f.up.nlev;
+  return LSBA_OK;
 }
 
 lsba_status lsba_solve_noalloc(lsba_context* c, const lsba_operator* op,

@@ -37,11 +37,13 @@ EXPORTS = [
     "lsba_solve_footprint", "lsba_server_create", "lsba_server_submit", "lsba_server_poll",
     "lsba_server_fetch", "lsba_server_stats", "lsba_server_destroy", "lsba_context_set_graphs",
     "lsba_solve_noalloc", "lsba_context_kernel_flops", "lsba_result_set_err_vs_ref",
-    "lsba_result_err_vs_ref",
+    "lsba_result_err_vs_ref", "lsba_precond_create_ilu0", "lsba_precond_destroy",
+    "lsba_precond_apply", "lsba_precond_factors", "lsba_precond_info", "lsba_solve_precond",
 ]
 
-KERNEL_KINDS = {"spmm": 0, "gram": 1, "gram_reduce": 2, "update": 3, "small": 4, "residual": 5}
-TIME_ALL = 0x3F
+KERNEL_KINDS = {"spmm": 0, "gram": 1, "gram_reduce": 2, "update": 3, "small": 4, "residual": 5,
+                "precond": 6}
+TIME_ALL = 0x7F
 
 
 class LibraryMissing(RuntimeError):
@@ -148,6 +150,14 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "lsba_server_stats": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(i32)]),
         "lsba_server_destroy": (None, [vp]),
+        "lsba_precond_create_ilu0": (i32, [vp, vp, ctypes.POINTER(vp)]),
+        "lsba_precond_destroy": (None, [vp]),
+        "lsba_precond_apply": (i32, [vp, vp, i32, vp, i64, vp, i64, ctypes.c_int]),
+        "lsba_precond_factors": (i32, [vp, vp, vp, vp]),
+        "lsba_precond_info": (i32, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                    ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "lsba_solve_precond": (i32, [vp, vp, vp, ctypes.POINTER(Params), i32, vp, i64, vp, i64,
+                                     ctypes.c_int, ctypes.POINTER(vp)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -276,6 +286,74 @@ class Operator:
             pass
 
 
+class Precond:
+    """ILU(0) factors of an operator's matrix, computed on the device
+    (lsba_precond_create_ilu0); pass as ``precond=`` to ``solve`` for right
+    preconditioning."""
+
+    def __init__(self, ctx: Context, op: Operator):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        st = ctx.lib.lsba_precond_create_ilu0(ctx.h, op.h, ctypes.byref(h))
+        if st != 0:
+            raise LsbaError(st, ctx.error())
+        self.h = h
+        n, nnz = ctypes.c_int64(), ctypes.c_int64()
+        lo, up = ctypes.c_int32(), ctypes.c_int32()
+        ctx.lib.lsba_precond_info(h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(lo),
+                                  ctypes.byref(up))
+        self.n, self.nnz = n.value, nnz.value
+        self.levels = (lo.value, up.value)
+
+    def factors(self):
+        """(row_ptr, col_idx, values) of the factors on A's pattern, columns
+        ascending: left of the diagonal L's multipliers, the rest U."""
+        rp = np.empty(self.n + 1, dtype=np.int64)
+        ci = np.empty(self.nnz, dtype=np.int32)
+        va = np.empty(self.nnz, dtype=np.float64)
+        st = self.ctx.lib.lsba_precond_factors(self.h, rp.ctypes.data_as(ctypes.c_void_p),
+                                               ci.ctypes.data_as(ctypes.c_void_p),
+                                               va.ctypes.data_as(ctypes.c_void_p))
+        if st != 0:
+            raise LsbaError(st, self.ctx.error())
+        return rp, ci, va
+
+    def apply(self, Y, Z=None):
+        """Z = U^{-1} L^{-1} Y (NumPy n x s, or torch CUDA tensors)."""
+        on_dev = _is_torch(Y)
+        if on_dev:
+            assert Y.stride(1) == 1
+            if Z is None:
+                import torch
+                Z = torch.empty_like(Y)
+            yp, ly = ctypes.c_void_p(Y.data_ptr()), Y.stride(0)
+            zp, lz = ctypes.c_void_p(Z.data_ptr()), Z.stride(0)
+            s = Y.shape[1]
+        else:
+            Y = np.ascontiguousarray(Y, dtype=np.float64)
+            s = Y.shape[1]
+            if Z is None:
+                Z = np.empty_like(Y)
+            yp, ly = Y.ctypes.data_as(ctypes.c_void_p), s
+            zp, lz = Z.ctypes.data_as(ctypes.c_void_p), s
+        st = self.ctx.lib.lsba_precond_apply(self.ctx.h, self.h, s, yp, ly, zp, lz,
+                                             1 if on_dev else 0)
+        if st != 0:
+            raise LsbaError(st, self.ctx.error())
+        return Z
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.lsba_precond_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 @dataclasses.dataclass
 class Result:
     status: str
@@ -314,11 +392,13 @@ def make_params(method="gmres", skeleton="bcgsi_ls", muscle="cholqr", precision=
     return p
 
 
-def solve(ctx: Context, op: Operator, B, X=None, x_ref=None, **kw) -> Result:
+def solve(ctx: Context, op: Operator, B, X=None, x_ref=None, precond: Precond | None = None,
+          **kw) -> Result:
     """Solve A X = B (B: n x s, row-major NumPy array or torch CUDA tensor).
     Keyword arguments are those of ``make_params``.  ``x_ref``: a reference
     solution (same kind of array as B, e.g. the FP64 oracle's X); the result
-    then carries ||X - x_ref||_F / ||x_ref||_F, formed by the library."""
+    then carries ||X - x_ref||_F / ||x_ref||_F, formed by the library.
+    ``precond``: ILU(0) factors for right preconditioning (lsba_solve_precond)."""
     lib = ctx.lib
     p = make_params(**kw)
     on_dev = _is_torch(B)
@@ -339,8 +419,12 @@ def solve(ctx: Context, op: Operator, B, X=None, x_ref=None, **kw) -> Result:
             X = np.empty_like(B)
         bptr, xptr, ldx = B.ctypes.data_as(ctypes.c_void_p), X.ctypes.data_as(ctypes.c_void_p), s
     h = ctypes.c_void_p()
-    st = lib.lsba_solve(ctx.h, op.h, ctypes.byref(p), s, bptr, ldb, xptr, ldx,
-                        1 if on_dev else 0, ctypes.byref(h))
+    if precond is None:
+        st = lib.lsba_solve(ctx.h, op.h, ctypes.byref(p), s, bptr, ldb, xptr, ldx,
+                            1 if on_dev else 0, ctypes.byref(h))
+    else:
+        st = lib.lsba_solve_precond(ctx.h, op.h, precond.h, ctypes.byref(p), s, bptr, ldb, xptr,
+                                    ldx, 1 if on_dev else 0, ctypes.byref(h))
     if st < 0:
         raise LsbaError(st, ctx.error())
     if x_ref is not None:

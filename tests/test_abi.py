@@ -15,7 +15,7 @@ def _declared():
     with open(os.path.join(ROOT, "include", "lsba.h")) as f:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lsba_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lsba_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -54,6 +54,12 @@ def test_null_handles_are_rejected(libh):
     libh.lsba_result_destroy(None)
     libh.lsba_context_destroy(None)
     libh.lsba_operator_destroy(None)
+    assert libh.lsba_precond_create_ilu0(None, None, None) == -1
+    assert libh.lsba_precond_apply(None, None, 1, None, 1, None, 1, 0) == -1
+    assert libh.lsba_precond_factors(None, None, None, None) == -1
+    assert libh.lsba_precond_info(None, None, None, None, None) == -1
+    assert libh.lsba_solve_precond(None, None, None, None, 1, None, 1, None, 1, 0, None) == -1
+    libh.lsba_precond_destroy(None)
 
 
 def test_params_struct_layout_matches_header():

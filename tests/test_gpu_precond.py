@@ -1,0 +1,212 @@
+"""Right ILU(0) preconditioning on the GPU against the oracle (Sec. 5, the
+tests on matrices from applications; ILU(0) = Gaussian elimination in row
+order restricted to A's pattern, right preconditioning A M^{-1} Y = B,
+X = M^{-1} Y).
+
+* Factors: the device factorization evaluates the elimination's products and
+  differences unfused and in the oracle's order, and divides with IEEE
+  division, so its factors equal the oracle's up to a few units in the last
+  place (the test prints how many entries are bit-identical).
+* Application: the sweeps sum each row's entries in ascending column order;
+  the oracle's triangular solves may sum in another order, so Z agrees to
+  1e-12 relative (max norm) on these well-conditioned factors.
+* Solves: X to 1e-10, identical iteration counts, restart points and counts.
+* Sizes cover chained runs of levels (one workgroup) and one-level launches
+  over many workgroups (3-D Laplacian at s = 32, a 2^16-node graph at s = 1)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from oracle.precond import ilu0, ilu0_apply
+from paper_2208_09899_amd import lsba, workloads as w
+
+from gpu_common import assert_parity, ctx
+
+pytestmark = pytest.mark.gpu
+
+
+def _shuffled_random(n, seed):
+    """Nonsymmetric pattern, diagonally dominant rows, columns stored in a
+    random order inside each row (the factorization sorts them)."""
+    rng = np.random.default_rng(seed)
+    M = sp.random(n, n, density=6.0 / n, random_state=rng, format="csr")
+    M.data = rng.standard_normal(M.data.shape[0])
+    M = (M + sp.diags(np.asarray(abs(M).sum(axis=1)).ravel() + 1.0 + rng.random(n))).tocsr()
+    M.sort_indices()
+    rp, ci, va = M.indptr.astype(np.int64), M.indices.copy(), M.data.copy()
+    for i in range(n):
+        a, b = rp[i], rp[i + 1]
+        p = rng.permutation(b - a)
+        ci[a:b] = ci[a:b][p]
+        va[a:b] = va[a:b][p]
+    return w.CSR(n=n, row_ptr=rp, col_idx=ci.astype(np.int32), values=va, name=f"rand{n}")
+
+
+CASES = {
+    "laplace2d_40": lambda: w.laplace_2d(40),
+    "convdiff_40": lambda: w.convdiff_2d(40, 8.0, 0.4),
+    "laplace3d_14": lambda: w.laplace_3d(14),
+    "rgg_4096": lambda: w.rgg_laplacian(1 << 12, seed=5, degree=6.0, shift=1e-3),
+    "random_shuffled_3000": lambda: _shuffled_random(3000, 7),
+}
+
+
+def _factors_dense_csr(pc):
+    rp, ci, va = pc.factors()
+    return sp.csr_matrix((va, ci, rp), shape=(pc.n, pc.n))
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_ilu0_factors_match_oracle(case):
+    A = CASES[case]()
+    op = lsba.Operator(ctx(), A)
+    pc = lsba.Precond(ctx(), op)
+    F = _factors_dense_csr(pc)
+    L, U = ilu0(A.to_scipy())
+    ref = (sp.tril(L, -1) + U).tocsr()
+    ref.sort_indices()
+    assert np.array_equal(F.indptr, ref.indptr) and np.array_equal(F.indices, ref.indices)
+    d = np.abs(F.data - ref.data)
+    rel = d / np.maximum(np.abs(ref.data), 1e-300)
+    print(f"{case}: n={A.n} nnz={A.nnz} levels={pc.levels} bit-identical "
+          f"{np.mean(d == 0):.4f} max rel diff {rel.max():.2e}")
+    assert rel.max() <= 1e-14
+    pc.close()
+    op.close()
+
+
+@pytest.mark.parametrize("s", [1, 3, 8, 16, 32])
+@pytest.mark.parametrize("case", ["convdiff_40", "laplace3d_14", "rgg_4096"])
+def test_ilu0_apply_matches_oracle(case, s):
+    A = CASES[case]()
+    op = lsba.Operator(ctx(), A)
+    pc = lsba.Precond(ctx(), op)
+    L, U = ilu0(A.to_scipy())
+    Y = w.rhs(A.n, s, seed=40 + s)
+    Z = pc.apply(Y)
+    Zo = ilu0_apply(L, U, Y)
+    err = np.abs(Z - Zo).max() / np.abs(Zo).max()
+    print(f"apply {case} s={s}: max rel diff {err:.2e}")
+    assert err <= 1e-12
+    pc.close()
+    op.close()
+
+
+def test_ilu0_apply_wide_levels_launch_many_workgroups():
+    """3-D Laplacian 24^3 at s = 32 (levels up to 432 rows > 128 per chained
+    pass) and a 2^16-node graph at s = 1 (levels up to ~12000 rows > 4096):
+    both sweeps run their wide levels as one-level launches."""
+    for A, s in ((w.laplace_3d(24), 32), (w.rgg_laplacian(1 << 16, seed=3, degree=4.0,
+                                                          shift=1e-3), 1)):
+        op = lsba.Operator(ctx(), A)
+        pc = lsba.Precond(ctx(), op)
+        L, U = ilu0(A.to_scipy())
+        Y = w.rhs(A.n, s, seed=9)
+        Z = pc.apply(Y)
+        Zo = ilu0_apply(L, U, Y)
+        err = np.abs(Z - Zo).max() / np.abs(Zo).max()
+        print(f"wide {A.name} s={s}: levels {pc.levels}, max rel diff {err:.2e}")
+        assert err <= 1e-12
+        pc.close()
+        op.close()
+
+
+def _solve_both(A, B, pc_kw, **kw):
+    op = lsba.Operator(ctx(), A)
+    pc = lsba.Precond(ctx(), op)
+    try:
+        g = lsba.solve(ctx(), op, B, precond=pc, true_res=True, **kw, **pc_kw)
+    finally:
+        pc.close()
+        op.close()
+    o = oracle.solve(A.to_scipy(), B, kw["method"], kw["skeleton"], kw.get("muscle", "cholqr"),
+                     m=kw["m"], tol=kw["tol"], max_cycles=kw["max_cycles"],
+                     precond=ilu0(A.to_scipy()))
+    return g, o
+
+
+@pytest.mark.parametrize("case,method,skel,s,m,tol,atol", [
+    ("convdiff_40", "gmres", "bcgsi_ls", 4, 20, 1e-10, 1e-12),
+    ("convdiff_40", "fom", "bmgs_cwy", 4, 20, 1e-10, 1e-12),
+    ("laplace2d_40", "gmres", "bmgs_svl", 8, 15, 1e-10, 1e-12),
+    ("laplace2d_40", "gmres", "bmgs_icwy", 8, 15, 1e-10, 1e-12),
+    ("laplace3d_14", "gmres", "bmgs_lts", 16, 10, 1e-10, 1e-12),
+    ("rgg_4096", "gmres", "bcgsi_ls", 5, 30, 1e-6, 1e-11),
+    ("rgg_4096", "gmres", "bmgs", 5, 30, 1e-6, 1e-11),
+    ("random_shuffled_3000", "gmres", "bcgsi_ls", 32, 8, 1e-10, 1e-12),
+])
+def test_preconditioned_solve_matches_oracle(case, method, skel, s, m, tol, atol):
+    A = CASES[case]()
+    B = w.rhs(A.n, s, seed=17)
+    g, o = _solve_both(A, B, {}, method=method, skeleton=skel, m=m, tol=tol, max_cycles=100)
+    print(f"precond {case} {method}/{skel} s={s}: iters {g.iters} (oracle {o.iters}), "
+          f"cycles {g.cycle_len}, true relres {g.true_relres:.2e}")
+    assert_parity(g, o, hist_atol=atol)
+    assert g.true_relres <= 1.05 * tol
+
+
+def test_preconditioning_cuts_iterations_and_replays_identically():
+    """Convection-diffusion 64^2, s = 8: ILU(0) cuts the block iterations
+    against the plain solve; cycle replay (hipGraphs holding the sweeps'
+    launches) gives bitwise the same X and history as eager launches."""
+    A = w.convdiff_2d(64, 5.0, 1.0)
+    B = w.rhs(A.n, 8, seed=2)
+    op = lsba.Operator(ctx(), A)
+    pc = lsba.Precond(ctx(), op)
+    kw = dict(method="gmres", skeleton="bcgsi_ls", m=20, tol=1e-10, max_cycles=200)
+    plain = lsba.solve(ctx(), op, B, **kw)
+    eager = lsba.solve(ctx(), op, B, precond=pc, **kw)
+    ctx().set_graphs(True)
+    try:
+        rep = [lsba.solve(ctx(), op, B, precond=pc, **kw) for _ in range(2)]
+    finally:
+        ctx().set_graphs(False)
+    print(f"convdiff 64^2: plain {plain.iters} iterations, ILU(0) {eager.iters}")
+    assert plain.status == "ok" and eager.status == "ok"
+    assert eager.iters * 3 <= plain.iters
+    for r in rep:
+        assert np.array_equal(r.X, eager.X)
+        assert np.array_equal(r.res_hist, eager.res_hist)
+    pc.close()
+    op.close()
+
+
+def test_precond_errors():
+    # missing diagonal entry
+    M = w.CSR(n=2, row_ptr=np.array([0, 2, 3], dtype=np.int64),
+              col_idx=np.array([0, 1, 0], dtype=np.int32), values=np.array([1.0, 2.0, 3.0]),
+              name="nodiag")
+    op = lsba.Operator(ctx(), M)
+    with pytest.raises(lsba.LsbaError) as e:
+        lsba.Precond(ctx(), op)
+    assert e.value.status == -1 and "diagonal" in str(e.value)
+    op.close()
+    # zero pivot in row 1: 6 - 3 * 2 = 0
+    Z = w.CSR(n=2, row_ptr=np.array([0, 2, 4], dtype=np.int64),
+              col_idx=np.array([1, 0, 0, 1], dtype=np.int32),
+              values=np.array([2.0, 1.0, 3.0, 6.0]), name="zeropiv")
+    op = lsba.Operator(ctx(), Z)
+    with pytest.raises(lsba.LsbaError) as e:
+        lsba.Precond(ctx(), op)
+    assert e.value.status == -1 and "row 1" in str(e.value)
+    op.close()
+    # mixed precision with a preconditioner, and a size mismatch
+    A = w.laplace_2d(8)
+    op = lsba.Operator(ctx(), A)
+    pc = lsba.Precond(ctx(), op)
+    B = w.rhs(A.n, 2, seed=1)
+    with pytest.raises(lsba.LsbaError) as e:
+        lsba.solve(ctx(), op, B, precond=pc, precision="mixed")
+    assert e.value.status == -4
+    op2 = lsba.Operator(ctx(), w.laplace_2d(9))
+    with pytest.raises(lsba.LsbaError) as e:
+        lsba.solve(ctx(), op2, w.rhs(81, 2, seed=1), precond=pc)
+    assert e.value.status == -1
+    # a preconditioner outlives its operator
+    op.close()
+    Zr = pc.apply(B)
+    L, U = ilu0(A.to_scipy())
+    assert np.abs(Zr - ilu0_apply(L, U, B)).max() <= 1e-12 * np.abs(Zr).max()
+    pc.close()
+    op2.close()
