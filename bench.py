@@ -41,7 +41,7 @@ BF16_SPLIT_PRODUCTS = 6    # FP32 products as six BF16 part products (three-part
 RGG_ITER_BUDGET = 500      # block iterations per solve on the random geometric graph
 
 WORKLOADS = {
-    # name: (workload key, scale, solve list [(method, skeleton)], precision, s, note)
+    # name: (workload key, scale, solve list [(method, skeleton)], precision[, preconditioner])
     "laplace2d": ("laplace2d", None,
                   [(m, k) for k in ("bcgsi_ls", "bmgs_cwy", "bmgs_icwy") for m in ("fom", "gmres")],
                   "fp64"),
@@ -50,6 +50,11 @@ WORKLOADS = {
     "rgg_mixed": ("rgg", None, [("gmres", "bcgsi_ls")], "mixed"),
     "laplace3d": ("laplace3d", None, [("gmres", "bcgsi_ls")], "fp64"),
     "laplace3d_mixed": ("laplace3d", None, [("gmres", "bcgsi_ls")], "mixed"),
+    # right ILU(0) preconditioning: the 2-D Laplacian of the FOM/GMRES
+    # comparison and a nonsymmetric convection-diffusion operator shaped like
+    # the paper's circuit-simulation test (s = 5, m = 10)
+    "laplace2d_ilu": ("laplace2d", None, [("gmres", "bcgsi_ls")], "fp64", "ilu0"),
+    "convdiff2d_ilu": ("convdiff2d", None, [("gmres", "bcgsi_ls")], "fp64", "ilu0"),
 }
 
 # HBM traffic of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
@@ -59,7 +64,7 @@ WORKLOADS = {
 def traffic_file(workload):
     return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
 KERNEL_SOURCES = {"update": "kernels_update.hip", "gram": "kernels_gram.hip",
-                  "spmm": "kernels_sparse.hip"}
+                  "spmm": "kernels_sparse.hip", "precond": "kernels_ilu.hip"}
 
 
 def kernel_source_hash(kind):
@@ -85,28 +90,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, solves, gpu_iters, budget_s=15.0, per_iteration=False):
+def cpu_baseline(wl, solves, gpu_iters, budget_s=15.0, per_iteration=False, precond=None):
     """Time the oracle on the host for a bounded number of block iterations of
     the first configured solve and scale to solves/s with the GPU's (identical)
-    iteration counts (or report block iterations/s for a budgeted workload)."""
+    iteration counts (or report block iterations/s for a budgeted workload).
+    With precond = "ilu0" the oracle's factorization is timed once and added
+    to each solve."""
     import threadpoolctl
 
     import oracle
     method, skel = solves[0]
     A = wl.A.to_scipy()
+    pre = None
+    t_fact = 0.0
+    if precond == "ilu0":
+        t0 = time.perf_counter()
+        pre = oracle.ilu0(A)
+        t_fact = time.perf_counter() - t0
     # calibrate: a few iterations, then a sample sized to the budget
     ncal = 2 if wl.A.n > 10 ** 6 else 5
     t0 = time.perf_counter()
     oracle.solve(A, wl.B, method, skel, "cholqr", m=wl.m, tol=0.0, max_cycles=10 ** 6,
-                 max_iters=ncal)
+                 max_iters=ncal, precond=pre)
     t_cal = (time.perf_counter() - t0) / ncal
     k = int(max(4, min(2000, budget_s / max(t_cal, 1e-6))))
     t0 = time.perf_counter()
     r = oracle.solve(A, wl.B, method, skel, "cholqr", m=wl.m, tol=0.0, max_cycles=10 ** 6,
-                     max_iters=k)
+                     max_iters=k, precond=pre)
     dt = time.perf_counter() - t0
     per_iter = dt / r.iters
-    step_s = per_iter * sum(gpu_iters)
+    step_s = per_iter * sum(gpu_iters) + t_fact * len(gpu_iters)
     threads = 1
     for info in threadpoolctl.threadpool_info():
         if info.get("internal_api") in ("openblas", "mkl", "blis"):
@@ -119,7 +132,10 @@ def cpu_baseline(wl, solves, gpu_iters, budget_s=15.0, per_iteration=False):
         "sample": (f"{r.iters} block iterations of {method}/{skel} (m={wl.m}) in {dt:.1f} s "
                    f"({per_iter * 1e3:.1f} ms/iteration), scaled by the GPU's iteration counts "
                    f"{list(gpu_iters)}; NumPy/SciPy FP64, BLAS threads {threads}, "
-                   f"scipy.sparse SpMM single-threaded"),
+                   f"scipy.sparse SpMM single-threaded"
+                   + (f"; right ILU(0), the oracle's factorization {t_fact:.1f} s per solve, "
+                      f"triangular solves by scipy.sparse.linalg.spsolve_triangular"
+                      if pre is not None else "")),
     }
 
 
@@ -221,7 +237,8 @@ def main():
 
     if args.workload == "serving":
         return run_serving(args, torch, lsba, w)
-    key, scale, solves, precision = WORKLOADS[args.workload]
+    key, scale, solves, precision = WORKLOADS[args.workload][:4]
+    precond = WORKLOADS[args.workload][4] if len(WORKLOADS[args.workload]) > 4 else None
     log(f"[bench] building workload {args.workload} ...")
     wl = w.workload(key, scale)
     n, s = wl.B.shape
@@ -231,7 +248,15 @@ def main():
     X = torch.empty_like(B)
     ctx = lsba.Context(0, stream="torch")
     op = lsba.Operator(ctx, wl.A)
+    pc, setup_ms = None, None
+    if precond == "ilu0":
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pc = lsba.Precond(ctx, op)
+        setup_ms = 1e3 * (time.perf_counter() - t0)
     kw = dict(m=wl.m, tol=wl.tol, max_cycles=wl.max_cycles, precision=precision)
+    if pc is not None:
+        kw["precond"] = pc
     # the random geometric graph of mean degree 4 lies below the 2-D
     # percolation threshold: many components with eigenvalues at the 1e-6
     # shift, and restarted BGMRES(25) does not reach 1e-8 in benchmark time,
@@ -267,7 +292,7 @@ def main():
         torch.cuda.synchronize()
         stats = ctx.kernel_stats()
         flops_prof = ctx.kernel_flops()
-        dom = max(("spmm", "gram", "update"), key=lambda k: stats[k][1])
+        dom = max(("spmm", "gram", "update", "precond"), key=lambda k: stats[k][1])
         # the timed steps bracket only the dominant class, which perturbs them least
         ctx.set_timing(True, kinds=[dom])
     log(f"[bench] timing {args.steps} steps of {len(solves)} solves")
@@ -314,10 +339,19 @@ def main():
                    "nnz": wl.A.nnz},
         "solves": res,
     }
+    if pc is not None:
+        # the factorization is made once per operator, outside the timed steps
+        line["config"]["precond"] = "right ILU(0)"
+        line["precond"] = {"kind": "ilu0", "setup_ms": round(setup_ms, 2),
+                           "levels_lower_upper": list(pc.levels)}
     if stats:
         hot = ("spmm", "gram", "gram_reduce", "update")
         tot_ms = sum(stats[k][1] for k in hot)
         tot_b = sum(stats[k][2] for k in ("spmm", "gram", "update"))
+        if pc is not None and stats["precond"][0]:
+            line["precond"]["apply_ms_per_iteration"] = round(
+                stats["precond"][1] / max(1, stats["spmm"][0]), 4)
+            line["precond"]["sweep_GBps"] = stats["precond"][2] / (stats["precond"][1] * 1e-3) / 1e9
         line["arnoldi_gbps"] = tot_b / (tot_ms * 1e-3) / 1e9 if tot_ms else None
         line["kernel_stats"] = {k: {"launches": v[0], "ms": round(v[1], 3),
                                     "alg_GB": round(v[2] / 1e9, 4)} for k, v in stats.items()}
@@ -325,6 +359,8 @@ def main():
                                      "first solve" if n * s > 10 ** 7 else "one whole step"))
         for k in ("spmm", "gram", "update"):
             line["kernel_stats"][k]["alg_GFLOP"] = round(flops_prof[k] / 1e9, 3)
+        if not stats["precond"][0]:
+            del line["kernel_stats"]["precond"]
         launches, ms, by = live[dom]
         fl = live_flops[dom]
         # roofline of the dominant class: the time its launches need at the
@@ -378,7 +414,8 @@ def main():
                 f"{tr['traffic_over_alg']:.3f} over {tr['launches']} launches of a capped run "
                 f"(profiles/traffic_{args.workload}.json), times this run's algorithmic bytes "
                 f"per launch")
-    if precision == "fp64" and not args.no_mixed and len(solves) == 1 and not budget:
+    if (precision == "fp64" and not args.no_mixed and len(solves) == 1 and not budget
+            and pc is None):
         # the precision form on the same problem, beside the headline (not in
         # the timed region): time to the same tolerance, true residual, and
         # its difference from the FP64 solution just computed
@@ -402,8 +439,10 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample ...")
         line["cpu_baseline"] = cpu_baseline(wl, solves, [r["iters"] for r in res],
-                                            per_iteration=bool(budget))
+                                            per_iteration=bool(budget), precond=precond)
     print(json.dumps(line), flush=True)
+    if pc is not None:
+        pc.close()
     op.close()
     ctx.close()
 

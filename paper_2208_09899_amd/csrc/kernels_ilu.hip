@@ -13,7 +13,12 @@
 // the previous level); runs of smaller levels are chained inside ONE
 // workgroup of 1024 threads with a workgroup barrier between levels, which
 // saves a launch per level where the graph's levels are narrow.  No kernel
-// waits on another workgroup.
+// waits on another workgroup.  In a chained run every thread solves at most
+// one row per level (a lane takes several columns when the widest level's
+// rows times the lanes per row exceed the workgroup), and the next level's
+// row, entry offsets, first entries and right-hand side are loaded before
+// the barrier, so that a level's critical path is the gather of the rows the
+// previous levels wrote.
 //
 // Sweep layout: positions in level order (rows of a level ascending), each
 // position's off-diagonal entries contiguous, so the lanes of a wavefront
@@ -30,7 +35,10 @@ namespace lsba {
 namespace {
 
 constexpr int kIluChainThreads = 1024;   // workgroup of a chained run of levels
-constexpr int kIluChainPasses = 4;       // a level is chained if it fits this many passes
+constexpr int kIluChainPasses = 4;       // factorization: a level is chained if it fits this
+                                         // many passes of the workgroup
+constexpr int kIluChainCols = 4;         // sweeps: most columns one lane takes in a chain
+constexpr int kIluChainLevels = 2048;    // most levels of one chained run (LDS offsets)
 constexpr int kIluThreads = 256;         // workgroup of a one-level launch
 constexpr int kIluMaxGrid = 1 << 16;
 
@@ -108,12 +116,116 @@ __global__ __launch_bounds__(kIluChainThreads) void ilu_sweep_kernel(
   }
 }
 
+// A chained run of levels [l0, l1) in one workgroup: thread t solves row
+// t >> lsh of each level (when the level has that many), columns
+// (t & (2^lsh - 1)) + q 2^lsh.  Every load a level issues is independent of
+// the others: the gathers of its own row (columns loaded a level earlier),
+// the right-hand side of the next level's row (row loaded a level earlier)
+// and the offsets, first entries and pivot of the row two levels on
+// (positions from the offsets staged in LDS).  The workgroup barrier between
+// levels drains them all, so a level costs one memory round trip.
+template <bool LOWER>
+__global__ __launch_bounds__(kIluChainThreads) void ilu_chain_kernel(
+    int s, int lsh, int l0, int l1, const int* __restrict__ lvl_ptr,
+    const int* __restrict__ rows, const int64_t* __restrict__ rp, const int* __restrict__ ci,
+    const double* __restrict__ v, const int* __restrict__ ecol, const double* __restrict__ eval,
+    const double* __restrict__ piv, const double* Y, double* Z, const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->stop) return;
+  __shared__ int sp[kIluChainLevels + 1];
+  const int nl = l1 - l0;
+  for (int t = threadIdx.x; t <= nl; t += blockDim.x) sp[t] = lvl_ptr[l0 + t];
+  __syncthreads();
+  const int L = 1 << lsh;
+  const int slot = threadIdx.x >> lsh;
+  const int c0 = threadIdx.x & (L - 1);
+  struct Row {
+    bool act;
+    int cnt;
+    int64_t i, p;
+    int col[kIluEll];
+    double val[kIluEll];
+    double d;
+  };
+  auto meta = [&](int l, Row& r) {
+    const int b = sp[l], e = sp[l + 1];
+    r.act = slot < e - b;
+    const int k = r.act ? b + slot : b;   // a valid position either way
+    r.i = rows[k];
+    r.p = rp[k];
+    r.cnt = (int)(rp[k + 1] - r.p);
+#pragma unroll
+    for (int u = 0; u < kIluEll; ++u) {
+      r.col[u] = ecol[(int64_t)k * kIluEll + u];
+      r.val[u] = eval[(int64_t)k * kIluEll + u];
+    }
+    r.d = LOWER ? 1.0 : piv[k];
+  };
+  auto rhs = [&](const Row& r, double (&y)[kIluChainCols]) {
+#pragma unroll
+    for (int q = 0; q < kIluChainCols; ++q) {
+      const int c = c0 + q * L;
+      y[q] = (r.act && c < s) ? Y[r.i * s + c] : 0.0;
+    }
+  };
+  Row cur, nxt;
+  double y[kIluChainCols];
+  meta(0, cur);
+  rhs(cur, y);
+  if (nl > 1) meta(1, nxt);
+  for (int l = 0; l < nl; ++l) {
+    double acc[kIluChainCols];
+#pragma unroll
+    for (int q = 0; q < kIluChainCols; ++q) acc[q] = y[q];
+    if (cur.act) {
+#pragma unroll
+      for (int u = 0; u < kIluEll; ++u) {
+        if (u < cur.cnt) {
+          const int64_t j = cur.col[u];
+#pragma unroll
+          for (int q = 0; q < kIluChainCols; ++q) {
+            const int c = c0 + q * L;
+            if (c < s) acc[q] -= cur.val[u] * Z[j * s + c];
+          }
+        }
+      }
+      for (int64_t p = cur.p + kIluEll; p < cur.p + cur.cnt; ++p) {
+        const int64_t j = ci[p];
+        const double vv = v[p];
+#pragma unroll
+        for (int q = 0; q < kIluChainCols; ++q) {
+          const int c = c0 + q * L;
+          if (c < s) acc[q] -= vv * Z[j * s + c];
+        }
+      }
+    }
+    Row nn{};
+    if (l + 1 < nl) rhs(nxt, y);
+    if (l + 2 < nl) meta(l + 2, nn);
+    if (cur.act) {
+#pragma unroll
+      for (int q = 0; q < kIluChainCols; ++q) {
+        const int c = c0 + q * L;
+        if (c < s) Z[cur.i * s + c] = LOWER ? acc[q] : acc[q] / cur.d;
+      }
+    }
+    if (l + 1 < nl) {
+      __syncthreads();
+      cur = nxt;
+      nxt = nn;
+    }
+  }
+}
+
+// dst[i] = src[map[i]], or 0 where map[i] < 0 (padding)
 __global__ __launch_bounds__(256) void ilu_gather_kernel(int64_t count,
                                                          const int64_t* __restrict__ map,
                                                          const double* __restrict__ src,
                                                          double* __restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) dst[i] = src[map[i]];
+  if (i < count) {
+    const int64_t m = map[i];
+    dst[i] = m >= 0 ? src[m] : 0.0;
+  }
 }
 
 void gather(hipStream_t st, int64_t count, const int64_t* map, const double* src, double* dst) {
@@ -123,25 +235,40 @@ void gather(hipStream_t st, int64_t count, const int64_t* map, const double* src
 }
 
 // Launch plan of a sweep for 2^lshift lanes per row (see the file comment).
+// Factorization (lshift = 0, one thread per row, several passes allowed):
+// levels of up to 4 workgroup passes are chained.  Sweeps: levels of up to
+// 1024 rows whose rows times lanes fit kIluChainCols columns per lane are
+// chained, with the lanes per row the widest level of the run allows.
 std::vector<IluLaunch> make_plan(const std::vector<int>& hptr, const std::vector<int64_t>& ents,
-                                 int lshift) {
+                                 int lshift, bool factor) {
   std::vector<IluLaunch> plan;
   const int nlev = (int)hptr.size() - 1;
-  const int64_t chain_rows = ((int64_t)kIluChainThreads * kIluChainPasses) >> lshift;
+  auto rows_of = [&](int l) { return (int64_t)hptr[l + 1] - hptr[l]; };
+  auto chainable = [&](int64_t r) {
+    if (factor) return r <= (int64_t)kIluChainThreads * kIluChainPasses;
+    return r <= kIluChainThreads && (r << lshift) <= (int64_t)kIluChainThreads * kIluChainCols;
+  };
   int l = 0;
   while (l < nlev) {
-    const int64_t r = hptr[l + 1] - hptr[l];
-    if (r > chain_rows) {
+    const int64_t r = rows_of(l);
+    if (!chainable(r)) {
       const int64_t thr = r << lshift;
       const int64_t g = std::min<int64_t>((thr + kIluThreads - 1) / kIluThreads, kIluMaxGrid);
-      plan.push_back({l, l + 1, (int)g, r, ents[l + 1] - ents[l]});
+      plan.push_back({l, l + 1, (int)g, lshift, r, ents[l + 1] - ents[l]});
       ++l;
-    } else {
-      int l1 = l + 1;
-      while (l1 < nlev && hptr[l1 + 1] - hptr[l1] <= chain_rows) ++l1;
-      plan.push_back({l, l1, 1, (int64_t)hptr[l1] - hptr[l], ents[l1] - ents[l]});
-      l = l1;
+      continue;
     }
+    int l1 = l;
+    int64_t maxr = 1;
+    while (l1 < nlev && chainable(rows_of(l1)) && l1 - l < kIluChainLevels) {
+      maxr = std::max(maxr, rows_of(l1));
+      ++l1;
+    }
+    int lsh = lshift;
+    if (!factor)
+      while (lsh > 0 && (maxr << lsh) > kIluChainThreads) --lsh;
+    plan.push_back({l, l1, 1, lsh, (int64_t)hptr[l1] - hptr[l], ents[l1] - ents[l]});
+    l = l1;
   }
   return plan;
 }
@@ -160,8 +287,8 @@ std::string dev_alloc(IluFactors& f, T** p, int64_t count) {
 // the map from each entry to its position in the sorted factor array.
 struct SweepHost {
   std::vector<int> ptr, rows;
-  std::vector<int64_t> rp, map, pivmap, lents;
-  std::vector<int> ci;
+  std::vector<int64_t> rp, map, pivmap, lents, emap;
+  std::vector<int> ci, ecol;
 };
 
 SweepHost analyse(int64_t n, const std::vector<int64_t>& srp, const std::vector<int>& sci,
@@ -201,13 +328,23 @@ SweepHost analyse(int64_t n, const std::vector<int64_t>& srp, const std::vector<
   }
   h.lents.resize(nl + 1);
   for (int l = 0; l <= nl; ++l) h.lents[l] = h.rp[h.ptr[l]];
+  // padded copy of each position's first kIluEll entries (map into the
+  // sweep's own entry array; -1: padding)
+  h.ecol.assign((size_t)n * kIluEll, 0);
+  h.emap.assign((size_t)n * kIluEll, -1);
+  for (int64_t k = 0; k < n; ++k)
+    for (int u = 0; u < kIluEll && h.rp[k] + u < h.rp[k + 1]; ++u) {
+      h.ecol[k * kIluEll + u] = h.ci[h.rp[k] + u];
+      h.emap[k * kIluEll + u] = h.rp[k] + u;
+    }
   return h;
 }
 
 // Copy one sweep's schedule to the device: its arrays are allocated into
 // `keep` (the factors), the entry maps of the set-up into `tmp`.
 std::string upload(hipStream_t st, IluFactors& keep, IluFactors& tmp, int64_t n, IluSweep& sw,
-                   const SweepHost& h, bool lower, int64_t** map_dev, int64_t** pivmap_dev) {
+                   const SweepHost& h, bool lower, int64_t** map_dev, int64_t** pivmap_dev,
+                   int64_t** emap_dev) {
   std::string e;
   const int64_t ne = (int64_t)h.ci.size();
   sw.nlev = (int)h.ptr.size() - 1;
@@ -217,6 +354,9 @@ std::string upload(hipStream_t st, IluFactors& keep, IluFactors& tmp, int64_t n,
   if (!(e = dev_alloc(keep, &sw.ci, ne)).empty()) return e;
   if (!(e = dev_alloc(keep, &sw.v, ne)).empty()) return e;
   if (!(e = dev_alloc(tmp, map_dev, ne)).empty()) return e;
+  if (!(e = dev_alloc(keep, &sw.ecol, n * kIluEll)).empty()) return e;
+  if (!(e = dev_alloc(keep, &sw.eval, n * kIluEll)).empty()) return e;
+  if (!(e = dev_alloc(tmp, emap_dev, n * kIluEll)).empty()) return e;
   if (!lower) {
     if (!(e = dev_alloc(keep, &sw.piv, n)).empty()) return e;
     if (!(e = dev_alloc(tmp, pivmap_dev, n)).empty()) return e;
@@ -228,10 +368,13 @@ std::string upload(hipStream_t st, IluFactors& keep, IluFactors& tmp, int64_t n,
             cp(sw.rows, h.rows.data(), sizeof(int) * n) &&
             cp(sw.rp, h.rp.data(), sizeof(int64_t) * (n + 1)) &&
             cp(sw.ci, h.ci.data(), sizeof(int) * ne) &&
-            cp(*map_dev, h.map.data(), sizeof(int64_t) * ne);
+            cp(*map_dev, h.map.data(), sizeof(int64_t) * ne) &&
+            cp(sw.ecol, h.ecol.data(), sizeof(int) * n * kIluEll) &&
+            cp(*emap_dev, h.emap.data(), sizeof(int64_t) * n * kIluEll);
   if (ok && !lower) ok = cp(*pivmap_dev, h.pivmap.data(), sizeof(int64_t) * n);
   if (!ok) return "copy of the ILU(0) level schedule failed";
-  for (int j = 0; j < 6; ++j) sw.plan[j] = make_plan(h.ptr, h.lents, j);
+  for (int j = 0; j < 6; ++j) sw.plan[j] = make_plan(h.ptr, h.lents, j, false);
+  sw.fplan = make_plan(h.ptr, h.lents, 0, true);
   return "";
 }
 
@@ -252,11 +395,16 @@ void launch_sweep(hipStream_t st, const IluSweep& sw, int s, const double* Y, do
     // levels, counted where they were written)
     const double bytes = 12.0 * (double)L.ents + (LOWER ? 12.0 : 20.0) * (double)L.rows +
                          16.0 * (double)L.rows * s;
-    const int block = L.grid == 1 ? kIluChainThreads : kIluThreads;
-    launch_k(tm, KK_PRECOND, bytes, ilu_sweep_kernel<LOWER>, dim3(L.grid), dim3(block), 0, st,
-             s, lsh, L.l0, L.l1, (const int*)sw.lvl_ptr, (const int*)sw.rows,
-             (const int64_t*)sw.rp, (const int*)sw.ci, (const double*)sw.v,
-             (const double*)sw.piv, Y, Z, ctl);
+    if (L.grid == 1)
+      launch_k(tm, KK_PRECOND, bytes, ilu_chain_kernel<LOWER>, dim3(1), dim3(kIluChainThreads),
+               0, st, s, L.lsh, L.l0, L.l1, (const int*)sw.lvl_ptr, (const int*)sw.rows,
+               (const int64_t*)sw.rp, (const int*)sw.ci, (const double*)sw.v,
+               (const int*)sw.ecol, (const double*)sw.eval, (const double*)sw.piv, Y, Z, ctl);
+    else
+      launch_k(tm, KK_PRECOND, bytes, ilu_sweep_kernel<LOWER>, dim3(L.grid), dim3(kIluThreads),
+               0, st, s, L.lsh, L.l0, L.l1, (const int*)sw.lvl_ptr, (const int*)sw.rows,
+               (const int64_t*)sw.rp, (const int*)sw.ci, (const double*)sw.v,
+               (const double*)sw.piv, Y, Z, ctl);
   }
 }
 
@@ -303,7 +451,7 @@ std::string ilu_build(hipStream_t st, int64_t n, int64_t nnz, const int64_t* rp_
   f.nnz_up = (int64_t)up.ci.size();
   std::string e;
   int64_t *perm_d = nullptr, *dg_d = nullptr, *lmap = nullptr, *umap = nullptr,
-          *pmap = nullptr, *unused = nullptr;
+          *pmap = nullptr, *unused = nullptr, *lemap = nullptr, *uemap = nullptr;
   unsigned long long* bad_d = nullptr;
   if (!(e = dev_alloc(f, &f.frp, n + 1)).empty()) return e;
   if (!(e = dev_alloc(f, &f.fci, nnz)).empty()) return e;
@@ -329,10 +477,12 @@ std::string ilu_build(hipStream_t st, int64_t n, int64_t nnz, const int64_t* rp_
           hipSuccess ||
       hipMemcpyAsync(bad_d, &none, sizeof(none), hipMemcpyHostToDevice, st) != hipSuccess)
     return fail_tmp("copy of the ILU(0) pattern failed");
-  if (!(e = upload(st, f, tmp, n, f.lo, lo, true, &lmap, &unused)).empty()) return fail_tmp(e);
-  if (!(e = upload(st, f, tmp, n, f.up, up, false, &umap, &pmap)).empty()) return fail_tmp(e);
+  if (!(e = upload(st, f, tmp, n, f.lo, lo, true, &lmap, &unused, &lemap)).empty())
+    return fail_tmp(e);
+  if (!(e = upload(st, f, tmp, n, f.up, up, false, &umap, &pmap, &uemap)).empty())
+    return fail_tmp(e);
   gather(st, nnz, perm_d, val_dev, f.fv);
-  for (const IluLaunch& L : f.lo.plan[0]) {
+  for (const IluLaunch& L : f.lo.fplan) {
     const int block = L.grid == 1 ? kIluChainThreads : kIluThreads;
     ilu_factor_kernel<<<dim3(L.grid), dim3(block), 0, st>>>(
         L.l0, L.l1, f.lo.lvl_ptr, f.lo.rows, f.frp, f.fci, dg_d, f.fv, bad_d);
@@ -340,6 +490,8 @@ std::string ilu_build(hipStream_t st, int64_t n, int64_t nnz, const int64_t* rp_
   gather(st, f.nnz_lo, lmap, f.fv, f.lo.v);
   gather(st, f.nnz_up, umap, f.fv, f.up.v);
   gather(st, n, pmap, f.fv, f.up.piv);
+  gather(st, n * kIluEll, lemap, f.lo.v, f.lo.eval);
+  gather(st, n * kIluEll, uemap, f.up.v, f.up.eval);
   unsigned long long bad = none;
   if (hipGetLastError() != hipSuccess ||
       hipMemcpyAsync(&bad, bad_d, sizeof(bad), hipMemcpyDeviceToHost, st) != hipSuccess ||

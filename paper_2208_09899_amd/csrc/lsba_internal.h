@@ -284,9 +284,11 @@ void launch_house(hipStream_t st, const Dense& d, int64_t n, int s, const T* X, 
 // entries of position k (strictly lower part for the forward sweep, strictly
 // upper part for the backward sweep) are ci/v[rp[k] .. rp[k+1]), columns
 // ascending; piv[k] is u_ii (backward sweep only).
+constexpr int kIluEll = 4;
 struct IluLaunch {
   int l0, l1;       // levels [l0, l1) of one launch
   int grid;         // workgroups (1: the levels are chained in one workgroup)
+  int lsh;          // 2^lsh lanes per row
   int64_t rows, ents;   // rows and off-diagonal entries the launch covers
 };
 struct IluSweep {
@@ -297,7 +299,12 @@ struct IluSweep {
   int* ci = nullptr;
   double* v = nullptr;
   double* piv = nullptr;
-  std::vector<IluLaunch> plan[6];   // launches for 2^j lanes per row, j = 0..5
+  // the first kIluEll entries of each position again, padded to that width
+  // (column 0, value 0 past the row's count): their loads need only k
+  int* ecol = nullptr;
+  double* eval = nullptr;
+  std::vector<IluLaunch> plan[6];   // sweep launches for 2^j lanes per row, j = 0..5
+  std::vector<IluLaunch> fplan;     // factorization launches (one thread per row)
 };
 // ILU(0) factors of a CSR matrix: the factors on A's pattern with each row's
 // columns sorted (fv: strictly lower part = L's multipliers, the rest = U),

@@ -324,6 +324,20 @@ void graph_put(lsba_context* c, std::vector<uint8_t> key, hipGraphExec_t ex) {
   c->graphs.push_back({std::move(key), ex, ++c->graph_tick});
 }
 
+// hipMemcpy2DAsync, or one contiguous copy when both pitches equal the row
+// width: a pitched copy to or from pageable host memory moves row by row,
+// which for millions of rows takes seconds.
+hipError_t copy2d(void* dst, size_t dp, const void* src, size_t sp, size_t w, size_t h,
+                  hipMemcpyKind kind, hipStream_t st) {
+  if (dp == w && sp == w) return hipMemcpyAsync(dst, src, w * h, kind, st);
+  return hipMemcpy2DAsync(dst, dp, src, sp, w, h, kind, st);
+}
+hipError_t copy2d_sync(void* dst, size_t dp, const void* src, size_t sp, size_t w, size_t h,
+                       hipMemcpyKind kind) {
+  if (dp == w && sp == w) return hipMemcpy(dst, src, w * h, kind);
+  return hipMemcpy2D(dst, dp, src, sp, w, h, kind);
+}
+
 void* ctx_buf(lsba_context* c, const std::string& name, size_t bytes) {
   auto& b = c->bufs[name];
   if (b.bytes < bytes) {
@@ -1665,7 +1679,7 @@ static lsba_status solve_impl(lsba_context* c, const lsba_operator* op, const ls
     double* B64 = (double*)ctx_buf(c, "B64", blk64);
     double* X64 = (double*)ctx_buf(c, "X64", blk64);
     HIPCHK(hipEventRecord(c->ev0, st));
-    HIPCHK(hipMemcpy2DAsync(B64, s * sizeof(double), B, ldb * sizeof(double), s * sizeof(double),
+    HIPCHK(copy2d(B64, s * sizeof(double), B, ldb * sizeof(double), s * sizeof(double),
                             n, in_kind, st));
     const double nB = device_norm(c, B64, n * s);
     r->have_loo = (p.record & LSBA_REC_LOO) != 0;
@@ -1728,7 +1742,7 @@ static lsba_status solve_impl(lsba_context* c, const lsba_operator* op, const ls
       if (r->status == LSBA_NOT_CONVERGED && rn / nB <= p.tol) r->status = LSBA_OK;
       r->true_relres = rn / nB;
     }
-    HIPCHK(hipMemcpy2DAsync(X, ldx * sizeof(double), X64, s * sizeof(double), s * sizeof(double),
+    HIPCHK(copy2d(X, ldx * sizeof(double), X64, s * sizeof(double), s * sizeof(double),
                             n, out_kind, st));
     HIPCHK(hipEventRecord(c->ev1, st));
     HIPCHK(hipEventSynchronize(c->ev1));
@@ -1824,11 +1838,11 @@ lsba_status lsba_precond_apply(lsba_context* c, const lsba_precond* pc, int32_t 
     const hipMemcpyKind in_kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     const hipMemcpyKind out_kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     double* W = (double*)ctx_buf(c, "PcW", (size_t)n * s * sizeof(double));
-    HIPCHK(hipMemcpy2DAsync(W, s * sizeof(double), Y, ldy * sizeof(double), s * sizeof(double),
+    HIPCHK(copy2d(W, s * sizeof(double), Y, ldy * sizeof(double), s * sizeof(double),
                             n, in_kind, st));
     launch_ilu_apply(st, pc->f, s, W, W, nullptr, c->timer);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpy2DAsync(Z, ldz * sizeof(double), W, s * sizeof(double), s * sizeof(double),
+    HIPCHK(copy2d(Z, ldz * sizeof(double), W, s * sizeof(double), s * sizeof(double),
                             n, out_kind, st));
     HIPCHK(hipStreamSynchronize(st));
     if (c->timer) c->timer->flush();
@@ -1913,7 +1927,7 @@ lsba_status lsba_solve_noalloc(lsba_context* c, const lsba_operator* op,
     Bump b{static_cast<char*>(g_scratch_ptr[c->device])};
     NoallocLayout L = noalloc_layout(b, n, s, p);
     HIPCHK(hipEventRecord(c->ev0, st));
-    HIPCHK(hipMemcpy2DAsync(L.B64, s * sizeof(double), B, ldb * sizeof(double),
+    HIPCHK(copy2d(L.B64, s * sizeof(double), B, ldb * sizeof(double),
                             s * sizeof(double), n, hipMemcpyDeviceToDevice, st));
     const double nB = device_norm(c, L.B64, n * s, &L.nw);
     r->have_loo = (p.record & LSBA_REC_LOO) != 0;
@@ -1931,7 +1945,7 @@ lsba_status lsba_solve_noalloc(lsba_context* c, const lsba_operator* op,
       if (p.record & LSBA_REC_TRUE_RES)
         r->true_relres = device_residual(c, op, s, L.X64, L.B64, nullptr, &L.nw) / nB;
     }
-    HIPCHK(hipMemcpy2DAsync(X, ldx * sizeof(double), L.X64, s * sizeof(double),
+    HIPCHK(copy2d(X, ldx * sizeof(double), L.X64, s * sizeof(double),
                             s * sizeof(double), n, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipEventRecord(c->ev1, st));
     HIPCHK(hipEventSynchronize(c->ev1));
@@ -2003,9 +2017,9 @@ lsba_status lsba_result_set_err_vs_ref(lsba_context* c, lsba_result* r, int64_t 
     if (!on_device) {
       double* a = (double*)ctx_buf(c, "cmp_x", blk);
       double* b = (double*)ctx_buf(c, "cmp_ref", blk);
-      HIPCHK(hipMemcpy2DAsync(a, s * sizeof(double), X, ldx * sizeof(double), s * sizeof(double),
+      HIPCHK(copy2d(a, s * sizeof(double), X, ldx * sizeof(double), s * sizeof(double),
                               n, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpy2DAsync(b, s * sizeof(double), Xref, ldr * sizeof(double),
+      HIPCHK(copy2d(b, s * sizeof(double), Xref, ldr * sizeof(double),
                               s * sizeof(double), n, hipMemcpyHostToDevice, st));
       Xd = a;
       Rd = b;
@@ -2024,7 +2038,7 @@ lsba_status lsba_result_set_err_vs_ref(lsba_context* c, lsba_result* r, int64_t 
     const double* Rc = Rd;
     if (lr != s) {
       double* b = (double*)ctx_buf(c, "cmp_ref", blk);
-      HIPCHK(hipMemcpy2DAsync(b, s * sizeof(double), Rd, lr * sizeof(double), s * sizeof(double),
+      HIPCHK(copy2d(b, s * sizeof(double), Rd, lr * sizeof(double), s * sizeof(double),
                               n, hipMemcpyDeviceToDevice, st));
       Rc = b;
     }
@@ -2130,7 +2144,7 @@ lsba_status lsba_server_submit(lsba_server* sv, const lsba_operator* op, const l
       delete r;
       return fail(c, LSBA_ERR_OOM, "pinned host allocation failed");
     }
-    HIPCHK(hipMemcpy2D(r->Bh, s * sizeof(double), B, ldb * sizeof(double), s * sizeof(double),
+    HIPCHK(copy2d_sync(r->Bh, s * sizeof(double), B, ldb * sizeof(double), s * sizeof(double),
                        r->n, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
   } catch (const HipError& e) {
     delete r->res;
@@ -2175,7 +2189,7 @@ lsba_status lsba_server_fetch(lsba_server* sv, uint64_t ticket, double* X, int64
   if (ldx < r->s) return fail(c, LSBA_ERR_ARG, "ldx must be >= s");
   try {
     HIPCHK(hipSetDevice(c->device));
-    HIPCHK(hipMemcpy2D(X, ldx * sizeof(double), r->Xh, r->s * sizeof(double),
+    HIPCHK(copy2d_sync(X, ldx * sizeof(double), r->Xh, r->s * sizeof(double),
                        r->s * sizeof(double), r->n,
                        on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
   } catch (const HipError& e) {

@@ -29,7 +29,8 @@ if __package__ in (None, ""):
 # kernel class: (kernel-name substrings, source file)
 KERNEL_CLASSES = {"update": (("update_kernel", "update_mfma"), "kernels_update.hip"),
                   "gram": (("gram_stage1", "gram_mfma"), "kernels_gram.hip"),
-                  "spmm": (("spmm_kernel", "spmm_coop_kernel"), "kernels_sparse.hip")}
+                  "spmm": (("spmm_kernel", "spmm_coop_kernel"), "kernels_sparse.hip"),
+                  "precond": (("ilu_sweep_kernel",), "kernels_ilu.hip")}
 
 
 def _counter_means(path, counter):
@@ -92,6 +93,8 @@ def main(argv=None):
     ap.add_argument("--skeleton", default="bcgsi_ls")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--max-iters", type=int, default=120)
+    ap.add_argument("--precond", choices=["none", "ilu0"], default="none",
+                    help="right ILU(0) preconditioning (factorization before the solve)")
     ap.add_argument("--copy", action="store_true",
                     help="run only a device-to-device copy of 512 MiB, 5 times")
     ap.add_argument("--stats", action="store_true",
@@ -127,17 +130,20 @@ def main(argv=None):
     X = torch.empty_like(B)
     ctx = lsba.Context(0, stream="torch")
     op = lsba.Operator(ctx, wl.A)
+    pc = lsba.Precond(ctx, op) if args.precond == "ilu0" else None
     if args.stats:
         ctx.set_timing(True)
     r = lsba.solve(ctx, op, B, X=X, method=args.method, skeleton=args.skeleton,
                    precision=args.precision, m=wl.m, tol=wl.tol, max_cycles=wl.max_cycles,
-                   max_iters=args.max_iters)
+                   max_iters=args.max_iters, precond=pc)
     torch.cuda.synchronize()
     out = {"workload": args.workload, "iters": r.iters, "status": r.status}
     if args.stats:
         out["kernel_stats"] = {k: {"launches": v[0], "ms": v[1], "alg_bytes": v[2]}
                                for k, v in ctx.kernel_stats().items()}
     print(json.dumps(out))
+    if pc is not None:
+        pc.close()
     op.close()
     ctx.close()
 

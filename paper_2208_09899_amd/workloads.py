@@ -229,6 +229,11 @@ def workload(name: str, scale: int | None = None) -> Workload:
         return Workload(name, rgg_laplacian(n, seed=3), rhs(n, 16, 4), m=25, tol=1e-8,
                         max_cycles=100000, methods=("gmres",), skeletons=("bcgsi_ls",),
                         note=f"RGG Laplacian n={n} + 1e-6 I, s=16, m=25, tol 1e-8")
+    if name == "convdiff2d":
+        N = scale or 256
+        return Workload(name, convdiff_2d(N, 10.0, 0.3), rhs(N * N, 5, 7), m=10, tol=1e-8,
+                        max_cycles=100000, methods=("gmres",), skeletons=("bcgsi_ls",),
+                        note=f"2-D convection-diffusion {N}x{N}, Peclet 10, s=5, m=10, tol 1e-8")
     if name == "laplace3d":
         N = scale or 128
         return Workload(name, laplace_3d(N), rhs(N ** 3, 32, 5), m=20, tol=1e-10,

@@ -76,7 +76,7 @@ def test_ilu0_factors_match_oracle(case):
     op.close()
 
 
-@pytest.mark.parametrize("s", [1, 3, 8, 16, 32])
+@pytest.mark.parametrize("s", [1, 3, 5, 8, 16, 32])
 @pytest.mark.parametrize("case", ["convdiff_40", "laplace3d_14", "rgg_4096"])
 def test_ilu0_apply_matches_oracle(case, s):
     A = CASES[case]()
@@ -94,9 +94,11 @@ def test_ilu0_apply_matches_oracle(case, s):
 
 
 def test_ilu0_apply_wide_levels_launch_many_workgroups():
-    """3-D Laplacian 24^3 at s = 32 (levels up to 432 rows > 128 per chained
-    pass) and a 2^16-node graph at s = 1 (levels up to ~12000 rows > 4096):
-    both sweeps run their wide levels as one-level launches."""
+    """3-D Laplacian 24^3 at s = 32 (levels up to 432 rows; a chained run
+    takes levels of up to 256 rows at s = 32) and a 2^16-node graph at s = 1
+    (levels up to ~12000 rows; chained runs take up to 1024): both sweeps run
+    their wide levels as one-level launches over many workgroups, and their
+    narrow levels chained."""
     for A, s in ((w.laplace_3d(24), 32), (w.rgg_laplacian(1 << 16, seed=3, degree=4.0,
                                                           shift=1e-3), 1)):
         op = lsba.Operator(ctx(), A)
