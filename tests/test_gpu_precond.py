@@ -212,3 +212,38 @@ def test_precond_errors():
     assert np.abs(Zr - ilu0_apply(L, U, B)).max() <= 1e-12 * np.abs(Zr).max()
     pc.close()
     op2.close()
+
+
+@pytest.mark.parametrize("wl_name", ["laplace2d", "convdiff2d"])
+def test_ilu0_full_size_workloads(wl_name):
+    """The two preconditioned benchmark workloads at full size (n = 65,536)
+    in the launch configuration bench.py times: every factor entry against
+    the oracle's, one application at the workload's s, and the first 35
+    block iterations of the solve (a whole cycle and the start of the next at
+    m = 30; three cycles and a half at m = 10) against the oracle's capped
+    solve -- X, histories, restart points and counts."""
+    wl = w.workload(wl_name)
+    A, B = wl.A, wl.B
+    op = lsba.Operator(ctx(), A)
+    pc = lsba.Precond(ctx(), op)
+    L, U = ilu0(A.to_scipy())
+    F = _factors_dense_csr(pc)
+    ref = (sp.tril(L, -1) + U).tocsr()
+    ref.sort_indices()
+    assert np.array_equal(F.indices, ref.indices)
+    rel = np.abs(F.data - ref.data) / np.maximum(np.abs(ref.data), 1e-300)
+    Z = pc.apply(B)
+    Zo = ilu0_apply(L, U, B)
+    zerr = np.abs(Z - Zo).max() / np.abs(Zo).max()
+    g = lsba.solve(ctx(), op, B, precond=pc, method="gmres", skeleton="bcgsi_ls", m=wl.m,
+                   tol=wl.tol, max_cycles=1000, max_iters=35)
+    pc.close()
+    op.close()
+    o = oracle.solve(A.to_scipy(), B, "gmres", "bcgsi_ls", "cholqr", m=wl.m, tol=wl.tol,
+                     max_cycles=1000, max_iters=35, precond=(L, U))
+    print(f"full size {wl_name}: levels {pc.levels}, factors max rel diff {rel.max():.2e}, "
+          f"apply {zerr:.2e}, capped solve {g.iters} iterations, cycles {g.cycle_len}")
+    assert rel.max() <= 1e-14
+    assert zerr <= 1e-12
+    assert g.status == o.status == "not_converged"
+    assert_parity(g, o)
