@@ -247,3 +247,59 @@ def test_ilu0_full_size_workloads(wl_name):
     assert zerr <= 1e-12
     assert g.status == o.status == "not_converged"
     assert_parity(g, o)
+
+
+def _csr_from_dense_pattern(M):
+    M = sp.csr_matrix(M)
+    M.sort_indices()
+    return w.CSR(n=M.shape[0], row_ptr=M.indptr.astype(np.int64),
+                 col_idx=M.indices.astype(np.int32), values=M.data.astype(np.float64),
+                 name="edge")
+
+
+@pytest.mark.parametrize("case", ["n1", "diagonal", "lower_bidiagonal_5000",
+                                  "upper_bidiagonal_5000"])
+def test_ilu0_degenerate_structures(case):
+    """Degenerate level structures: one row; a diagonal matrix (one level per
+    sweep, no off-diagonal entries); bidiagonal matrices whose one sweep has
+    5000 levels of one row (more than one chained launch holds, so the run
+    is split) while the other sweep has a single level.  The factors of a
+    diagonal or bidiagonal matrix are exact (no fill), so M^{-1} = A^{-1}:
+    the preconditioned solve takes one block column."""
+    rng = np.random.default_rng(3)
+    if case == "n1":
+        M = sp.csr_matrix(np.array([[2.5]]))
+    elif case == "diagonal":
+        M = sp.diags(1.0 + rng.random(1000)).tocsr()
+    else:
+        n = 5000
+        off = rng.uniform(-0.9, 0.9, n - 1)
+        M = sp.diags([1.0 + rng.random(n), off], [0, -1 if case.startswith("lower") else 1]).tocsr()
+    A = _csr_from_dense_pattern(M)
+    op = lsba.Operator(ctx(), A)
+    pc = lsba.Precond(ctx(), op)
+    L, U = ilu0(A.to_scipy())
+    for s in (1, 4, 32):
+        Y = w.rhs(A.n, s, seed=s)
+        Z = pc.apply(Y)
+        Zo = ilu0_apply(L, U, Y)
+        assert np.abs(Z - Zo).max() <= 1e-12 * np.abs(Zo).max(), (case, s)
+    if A.n == 1:
+        # the factorization and sweeps of a single row; a solve with one
+        # unknown is not a case of the method (its one-dimensional Krylov
+        # space ends in a Cholesky flag before the first column is final)
+        pc.close()
+        op.close()
+        return
+    B = w.rhs(A.n, 3, seed=8)
+    g = lsba.solve(ctx(), op, B, precond=pc, true_res=True, method="gmres",
+                   skeleton="bcgsi_ls", m=5, tol=1e-10, max_cycles=10)
+    o = oracle.solve(A.to_scipy(), B, "gmres", "bcgsi_ls", "cholqr", m=5, tol=1e-10,
+                     max_cycles=10, precond=(L, U))
+    print(f"{case}: levels {pc.levels}, status {g.status} (oracle {o.status}), iterations "
+          f"{g.iters}, true relres {g.true_relres:.1e}")
+    assert_parity(g, o)
+    # M = A up to rounding: the first block column solves the system
+    assert g.status == "ok" and g.iters == 1 and g.true_relres <= 1e-10
+    pc.close()
+    op.close()
