@@ -366,6 +366,125 @@ __device__ void cycle_end_regs(const Dense& d, int j, bool want_m, double* lds) 
   bar();
 }
 
+// The same results for any j s^2 (the register form above needs
+// j s^2 <= kCeRegs NT): left-looking block back substitution, block b's
+// right-hand side g_b - R_{b, b+1:j} Xi_{b+1:j} accumulated over chunks of
+// kCeChunk solved rows staged in LDS (with the matching columns of R's block
+// row), then the s x s triangular solve with R_bb in LDS, one thread per
+// column.  Xi goes to d.Xi (read back by the later blocks' chunks) and to
+// the update coefficients.  M's recurrence stages each Q_i slice in LDS.
+constexpr int kCeChunk = 128;
+constexpr int kCeOut = (kMaxS * kMaxS + NT - 1) / NT;
+__device__ void cycle_end_tiled(const Dense& d, int j, bool want_m, double* lds) {
+  const int s = d.s, ld = d.ldh, ss = s * s, js = j * s;
+  CoefLayout lay{s, d.mmax + 1};
+  const int tid = threadIdx.x;
+  double* Xb = lds;                     // ss
+  double* Rbb = Xb + ss;                // ss
+  double* Rch = Rbb + ss;               // s x kCeChunk
+  double* Xch = Rch + s * kCeChunk;     // kCeChunk x s
+  double* coefA = d.coef64 + lay.A(0);
+  for (int bb = j - 1; bb >= 0; --bb) {
+    const int r0 = bb * s;
+    const bool last = bb == j - 1;
+    double acc[kCeOut];
+#pragma unroll
+    for (int q = 0; q < kCeOut; ++q) acc[q] = 0.0;
+    for (int k0 = r0 + s; k0 < js; k0 += kCeChunk) {
+      const int kc = min(kCeChunk, js - k0);
+      for (int e = tid; e < s * kc; e += NT) {
+        const int r = e / kc, t = e % kc;
+        Rch[r * kCeChunk + t] = d.Rf[(int64_t)(r0 + r) * ld + k0 + t];
+      }
+      for (int e = tid; e < kc * s; e += NT) Xch[e] = d.Xi[(int64_t)k0 * s + e];
+      bar();
+#pragma unroll
+      for (int q = 0; q < kCeOut; ++q) {
+        const int e = tid + q * NT;
+        if (e < ss) {
+          const int r = e / s, c = e % s;
+          const double* ra = Rch + r * kCeChunk;
+          double a0 = 0.0, a1 = 0.0;
+          int t = 0;
+          for (; t + 1 < kc; t += 2) {
+            a0 = fma(ra[t], Xch[t * s + c], a0);
+            a1 = fma(ra[t + 1], Xch[(t + 1) * s + c], a1);
+          }
+          if (t < kc) a0 = fma(ra[t], Xch[t * s + c], a0);
+          acc[q] += a0 + a1;
+        }
+      }
+      bar();
+    }
+    // right-hand side of the block and its diagonal block of R
+#pragma unroll
+    for (int q = 0; q < kCeOut; ++q) {
+      const int e = tid + q * NT;
+      if (e < ss) {
+        const double rhs = (last && d.method == LSBA_FOM) ? d.ylast[e]
+                                                          : d.g[(int64_t)r0 * s + e];
+        Xb[e] = rhs - acc[q];
+        Rbb[e] = d.Rf[(int64_t)(r0 + e / s) * ld + r0 + e % s];
+      }
+    }
+    bar();
+    // FOM's last block comes with the column's test; every other block
+    // solves R_bb x = (its right-hand side)
+    if (!(last && d.method == LSBA_FOM) && tid < s) {
+      const int c = tid;
+      for (int r = s - 1; r >= 0; --r) {
+        double v = Xb[r * s + c];
+        for (int t = r + 1; t < s; ++t) v = fma(-Rbb[r * s + t], Xb[t * s + c], v);
+        Xb[r * s + c] = v / Rbb[r * s + r];
+      }
+    }
+    bar();
+    for (int e = tid; e < ss; e += NT) {
+      d.Xi[(int64_t)r0 * s + e] = Xb[e];
+      coefA[(int64_t)bb * ss + e] = Xb[e];
+    }
+    bar();
+  }
+  if (!want_m) return;
+  double* w0 = Rch;           // ss
+  double* w1 = w0 + ss;       // ss
+  double* Dt = w1 + ss;       // ss
+  double* Qsl = Dt + ss;      // s x 2s: rows s..2s of Q_i^T
+  // S = D^{-T} (H_{j+1,j}^T H_{j+1,j})
+  const double* Hsub = d.H + (int64_t)js * ld + (j - 1) * s;
+  for (int e = tid; e < ss; e += NT) {
+    const int r = e / s, c = e % s;
+    double x = 0.0;
+    for (int t = 0; t < s; ++t) x = fma(Hsub[(int64_t)t * ld + r], Hsub[(int64_t)t * ld + c], x);
+    w0[e] = x;
+    Dt[e] = d.Dlast[c * s + r];
+  }
+  bar();
+  lu_solve(Dt, w0, s, s);
+  bar();
+  double* coefB = d.coef64 + lay.B(0);
+  double* wc = w0;
+  double* wn = w1;
+  for (int i = j - 1; i >= 1; --i) {
+    const double* Qg = d.Qt + (int64_t)(i - 1) * 4 * ss + 2 * ss;
+    for (int e = tid; e < 2 * ss; e += NT) Qsl[e] = Qg[e];
+    bar();
+    for (int e = tid; e < 2 * ss; e += NT) {
+      const int r = e / s, c = e % s;
+      double x = 0.0;
+      for (int t = 0; t < s; ++t) x = fma(Qsl[t * 2 * s + r], wc[t * s + c], x);
+      if (r < s) wn[r * s + c] = x;
+      else coefB[(int64_t)i * ss + (r - s) * s + c] = x;
+    }
+    bar();
+    double* t = wc;
+    wc = wn;
+    wn = t;
+  }
+  for (int e = tid; e < ss; e += NT) coefB[e] = wc[e];
+  bar();
+}
+
 // End of a cycle: Xi, M, the cospatial factor, the basis-application
 // coefficients and the adaptive restart bookkeeping.
 __global__ __launch_bounds__(NT) void small_cycle_end_kernel(Dense d) {
@@ -403,46 +522,8 @@ __global__ __launch_bounds__(NT) void small_cycle_end_kernel(Dense d) {
     cycle_end_regs(d, j, want_m, lds);
     xlast = d.coef64 + lay.A(j - 1);
   } else {
-    double* Xi = d.Xi;
-    // last block of Xi
-    if (d.method == LSBA_FOM) {
-      copy(s, s, d.ylast, s, Xi + (int64_t)c0 * s, s);
-    } else {
-      copy(s, s, d.g + (int64_t)c0 * s, s, Xi + (int64_t)c0 * s, s);
-      tri_solve_up(d.Rf + (int64_t)c0 * ld + c0, ld, s, Xi + (int64_t)c0 * s, s, s);
-    }
-    // block back substitution with the triangular factor
-    for (int b = j - 1; b >= 1; --b) {
-      const int rb = (b - 1) * s;
-      double* xb = Xi + (int64_t)rb * s;
-      copy(s, s, d.g + (int64_t)rb * s, s, xb, s);
-      mm(s, s, js - (rb + s), -1.0, d.Rf + (int64_t)rb * ld + rb + s, ld, false,
-         Xi + (int64_t)(rb + s) * s, s, false, 1.0, xb, s);
-      tri_solve_up(d.Rf + (int64_t)rb * ld + rb, ld, s, xb, s, s);
-    }
-    copy(js, s, Xi, s, d.coef64 + lay.A(0), s);
-    if (want_m) {
-      // M = Q_1 ... Q_{j-1} E_j D^{-T} (H_{j+1,j}^T H_{j+1,j})
-      const double* Hsub = d.H + (int64_t)js * ld + c0;
-      double* S = sc.sm(2);
-      mm(s, s, s, 1.0, Hsub, ld, true, Hsub, ld, false, 0.0, S, s);
-      double* Dt = sc.sm(3);
-      for (int e = threadIdx.x; e < ss; e += NT) Dt[e] = d.Dlast[(e % s) * s + (e / s)];
-      bar();
-      lu_solve(Dt, S, s, s);
-      fill(js, s, 0.0, d.M, s);
-      copy(s, s, S, s, d.M + (int64_t)c0 * s, s);
-      // apply Q_i = (Q_i^T)^T to rows (i-1)s..(i+1)s, i = j-1 .. 1
-      double* w2 = sc.sm(4);   // 2s x s
-      for (int i = j - 1; i >= 1; --i) {
-        double* Mw = d.M + (int64_t)(i - 1) * ss;
-        mm(2 * s, s, 2 * s, 1.0, d.Qt + (int64_t)(i - 1) * 4 * ss, 2 * s, true, Mw, s, false,
-           0.0, w2, s);
-        copy(2 * s, s, w2, s, Mw, s);
-      }
-      copy(js, s, d.M, s, d.coef64 + lay.B(0), s);
-    }
-    xlast = Xi + (int64_t)c0 * s;
+    cycle_end_tiled(d, j, want_m, lds);
+    xlast = d.coef64 + lay.A(j - 1);
   }
   int nvb = 0, nve = 0;
   if (!final_) {
