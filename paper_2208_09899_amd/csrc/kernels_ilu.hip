@@ -426,6 +426,8 @@ std::string ilu_build(hipStream_t st, int64_t n, int64_t nnz, const int64_t* rp_
   *bad_row = -1;
   f.n = n;
   f.nnz = nnz;
+  // level positions and row indices are 32-bit
+  if (n >= (int64_t)INT_MAX) return "ILU(0) needs n < 2^31 - 1";
   // rows with sorted columns; perm maps a sorted position to A's position
   std::vector<int64_t> srp(rp_h, rp_h + n + 1), perm(nnz), dg(n, -1);
   std::vector<int> sci(nnz);

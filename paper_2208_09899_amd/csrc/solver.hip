@@ -98,8 +98,7 @@ struct lsba_operator {
 // Right ILU(0) preconditioner of an operator (factors in device memory).
 struct lsba_precond {
   lsba_context* ctx = nullptr;
-  const lsba_operator* op = nullptr;
-  IluFactors f;
+  IluFactors f;   // holds no reference to the operator it was made from
 };
 
 struct lsba_result {
@@ -1789,7 +1788,6 @@ lsba_status lsba_precond_create_ilu0(lsba_context* c, const lsba_operator* op,
   auto* pc = new (std::nothrow) lsba_precond();
   if (!pc) return fail(c, LSBA_ERR_OOM, "host allocation failed");
   pc->ctx = c;
-  pc->op = op;
   try {
     HIPCHK(hipSetDevice(c->device));
     std::vector<int64_t> rp(op->n + 1);
