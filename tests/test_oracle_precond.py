@@ -192,3 +192,28 @@ def test_right_preconditioned_convdiff_residual_and_error(skel):
     Xd = np.linalg.solve(Ad, B)
     kap = np.linalg.cond(Ad)
     assert np.linalg.norm(pre.X - Xd) / np.linalg.norm(Xd) <= kap * 2 * tol
+
+
+@pytest.mark.parametrize("skel", ["bcgsi_ls", "bmgs_cwy", "bmgs_svl", "bmgs"])
+def test_right_preconditioned_arnoldi_relation(skel):
+    """One cycle on A M^{-1}: the block Arnoldi relation (Sec. 2.4, eq.
+    block_arnoldi) holds for the operator formed independently as the dense
+    product A (L U)^{-1} (a dense LU solve, not the oracle's triangular
+    sweeps), to 1e-12.  (The basis's loss of orthogonality is the skeleton's
+    own, O(u kappa) of the Krylov basis, and is not bounded here.)"""
+    from oracle.precond import RightPreconditioned
+    from oracle.skeletons import Counters, make_skeleton
+    A = w.convdiff_2d(20, 6.0, 0.7).to_scipy()
+    B = w.rhs(A.shape[0], 3, seed=4)
+    L, U = ilu0(A)
+    sk = make_skeleton(skel, RightPreconditioned(A, L, U), 3, 15, "cholqr", Counters())
+    j = 0
+    for jj in sk.run(B):
+        j = jj
+    assert j >= 14
+    Md = (L @ U).toarray()
+    AMinv = np.linalg.solve(Md.T, A.toarray().T).T       # A M^{-1}
+    Vj, Vj1 = sk.Vcat(j), sk.Vcat(j + 1)
+    lhs = AMinv @ Vj
+    rel = np.linalg.norm(lhs - Vj1 @ sk.Hm1m(j)) / np.linalg.norm(lhs)
+    assert rel <= 1e-12, rel
