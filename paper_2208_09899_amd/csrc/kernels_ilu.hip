@@ -15,15 +15,19 @@
 // saves a launch per level where the graph's levels are narrow.  No kernel
 // waits on another workgroup.  In a chained run every thread solves at most
 // one row per level (a lane takes several columns when the widest level's
-// rows times the lanes per row exceed the workgroup), and the next level's
-// row, entry offsets, first entries and right-hand side are loaded before
-// the barrier, so that a level's critical path is the gather of the rows the
-// previous levels wrote.
+// rows times the lanes per row exceed the workgroup), and the loads a level
+// issues are independent of each other (its own gathers, the next level's
+// right-hand side, the row data of the level after that).  The barrier
+// between levels drains every load in flight, so a level costs one memory
+// round trip plus the barrier; row data that is cold in L2 sets that round
+// trip's length.
 //
 // Sweep layout: positions in level order (rows of a level ascending), each
 // position's off-diagonal entries contiguous, so the lanes of a wavefront
 // read neighbouring rows' entries and the s lanes of a row read s contiguous
-// elements of each gathered row of the block.
+// elements of each gathered row of the block; the first kIluEll entries of
+// every position are repeated in a padded fixed-width array, so that their
+// addresses follow from the position alone.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -85,9 +89,12 @@ __global__ __launch_bounds__(kIluChainThreads) void ilu_factor_kernel(
   }
 }
 
-// One sweep over levels [l0, l1): 2^lshift lanes per row, lane c < s owns
-// column c.  Forward (LOWER): z_i = y_i - sum_j l_ij z_j; backward:
-// x_i = (z_i - sum_j u_ij x_j) / u_ii.  Y and Z may be the same block.
+// One wide level of a sweep (l1 = l0 + 1) over many workgroups: 2^lshift
+// lanes per row, lane c < s owns column c.  Forward (LOWER):
+// z_i = y_i - sum_j l_ij z_j; backward: x_i = (z_i - sum_j u_ij x_j) / u_ii.
+// Y and Z may be the same block.  (With one workgroup it would also chain
+// levels [l0, l1) behind barriers; the launch plan uses ilu_chain_kernel
+// for that.)
 template <bool LOWER>
 __global__ __launch_bounds__(kIluChainThreads) void ilu_sweep_kernel(
     int s, int lshift, int l0, int l1, const int* __restrict__ lvl_ptr,
