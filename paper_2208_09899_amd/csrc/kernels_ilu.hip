@@ -429,8 +429,10 @@ void ilu_free(IluFactors& f) {
 
 // On failure the caller releases f with ilu_free.
 std::string ilu_build(hipStream_t st, int64_t n, int64_t nnz, const int64_t* rp_h,
-                      const int* ci_h, const double* val_dev, IluFactors& f, int64_t* bad_row) {
+                      const int* ci_h, const double* val_dev, IluFactors& f, int64_t* bad_row,
+                      bool* bad_input) {
   *bad_row = -1;
+  *bad_input = true;
   f.n = n;
   f.nnz = nnz;
   // level positions and row indices are 32-bit
@@ -454,6 +456,7 @@ std::string ilu_build(hipStream_t st, int64_t n, int64_t nnz, const int64_t* rp_
     }
     if (dg[i] < 0) return "row " + std::to_string(i) + " stores no diagonal entry";
   }
+  *bad_input = false;   // from here on, failures are the device's
   const SweepHost lo = analyse(n, srp, sci, dg, true);
   const SweepHost up = analyse(n, srp, sci, dg, false);
   f.nnz_lo = (int64_t)lo.ci.size();
@@ -509,6 +512,7 @@ std::string ilu_build(hipStream_t st, int64_t n, int64_t nnz, const int64_t* rp_
   ilu_free(tmp);
   if (bad != none) {
     *bad_row = (int64_t)bad;
+    *bad_input = true;
     return "zero or non-finite pivot in row " + std::to_string(bad);
   }
   return "";

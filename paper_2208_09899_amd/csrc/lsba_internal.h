@@ -319,10 +319,13 @@ struct IluFactors {
 };
 // Analyse the pattern (host copies of A's row pointer and column indices),
 // then factor A's values (device) on st.  Returns "" on success, else the
-// reason (missing diagonal, duplicate column, allocation or HIP failure;
-// for a zero or non-finite pivot *bad_row receives its row, else -1).
+// reason; *bad_input is true when the matrix itself is the reason (n too
+// large, a missing diagonal, a duplicate column, a zero or non-finite pivot,
+// whose row *bad_row receives; else -1) and false for allocation or HIP
+// failures.
 std::string ilu_build(hipStream_t st, int64_t n, int64_t nnz, const int64_t* rp_h,
-                      const int* ci_h, const double* val_dev, IluFactors& f, int64_t* bad_row);
+                      const int* ci_h, const double* val_dev, IluFactors& f, int64_t* bad_row,
+                      bool* bad_input);
 void ilu_free(IluFactors& f);
 // Z = U^{-1} L^{-1} Y for n x s row-major blocks (Z may alias Y).
 void launch_ilu_apply(hipStream_t st, const IluFactors& f, int s, const double* Y, double* Z,

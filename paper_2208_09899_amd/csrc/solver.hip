@@ -1796,13 +1796,16 @@ lsba_status lsba_precond_create_ilu0(lsba_context* c, const lsba_operator* op,
     if (op->nnz)
       HIPCHK(hipMemcpy(ci.data(), op->ci, sizeof(int) * op->nnz, hipMemcpyDeviceToHost));
     int64_t bad = -1;
-    const std::string e =
-        ilu_build(c->stream, op->n, op->nnz, rp.data(), ci.data(), op->val, pc->f, &bad);
+    bool bad_input = false;
+    const std::string e = ilu_build(c->stream, op->n, op->nnz, rp.data(), ci.data(), op->val,
+                                    pc->f, &bad, &bad_input);
     if (!e.empty()) {
       precond_release(pc);
       delete pc;
-      const bool arg = bad >= 0 || e.find("row ") == 0;
-      return fail(c, arg ? LSBA_ERR_ARG : LSBA_ERR_HIP, e);
+      const lsba_status st = bad_input                                  ? LSBA_ERR_ARG
+                             : e.find("device allocation") == 0 ? LSBA_ERR_OOM
+                                                                : LSBA_ERR_HIP;
+      return fail(c, st, e);
     }
   } catch (const HipError& e) {
     precond_release(pc);
