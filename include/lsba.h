@@ -224,8 +224,9 @@ lsba_status lsba_solve(lsba_context* ctx, const lsba_operator* op, const lsba_pa
 typedef struct lsba_precond lsba_precond;
 
 /* Factor op's matrix.  Every row must store its diagonal entry and no column
- * twice (else LSBA_ERR_ARG); a zero or non-finite pivot u_ii is LSBA_ERR_ARG
- * with the row in lsba_last_error.  The factors are device memory owned by
+ * twice, and n < 2^31 - 1 (else LSBA_ERR_ARG); a zero or non-finite pivot
+ * u_ii is LSBA_ERR_ARG with the row in lsba_last_error; LSBA_ERR_OOM when the
+ * factors' device memory cannot be allocated.  The factors are device memory owned by
  * the handle; op may be destroyed afterwards.  Destroying the context first
  * releases the factors (lsba_precond_destroy then frees only the handle). */
 lsba_status lsba_precond_create_ilu0(lsba_context* ctx, const lsba_operator* op,
