@@ -38,13 +38,6 @@ namespace lsba {
 
 namespace {
 
-constexpr int kIluChainThreads = 1024;   // workgroup of a chained run of levels
-constexpr int kIluChainPasses = 4;       // factorization: a level is chained if it fits this
-                                         // many passes of the workgroup
-constexpr int kIluChainCols = 4;         // sweeps: most columns one lane takes in a chain
-constexpr int kIluChainLevels = 2048;    // most levels of one chained run (LDS offsets)
-constexpr int kIluThreads = 256;         // workgroup of a one-level launch
-constexpr int kIluMaxGrid = 1 << 16;
 
 // Factorization of the rows of levels [l0, l1) (one thread per row).  The
 // updates are evaluated as written (no fused multiply-add), the order of the
@@ -241,45 +234,6 @@ void gather(hipStream_t st, int64_t count, const int64_t* map, const double* src
   ilu_gather_kernel<<<dim3((unsigned)g), dim3(256), 0, st>>>(count, map, src, dst);
 }
 
-// Launch plan of a sweep for 2^lshift lanes per row (see the file comment).
-// Factorization (lshift = 0, one thread per row, several passes allowed):
-// levels of up to 4 workgroup passes are chained.  Sweeps: levels of up to
-// 1024 rows whose rows times lanes fit kIluChainCols columns per lane are
-// chained, with the lanes per row the widest level of the run allows.
-std::vector<IluLaunch> make_plan(const std::vector<int>& hptr, const std::vector<int64_t>& ents,
-                                 int lshift, bool factor) {
-  std::vector<IluLaunch> plan;
-  const int nlev = (int)hptr.size() - 1;
-  auto rows_of = [&](int l) { return (int64_t)hptr[l + 1] - hptr[l]; };
-  auto chainable = [&](int64_t r) {
-    if (factor) return r <= (int64_t)kIluChainThreads * kIluChainPasses;
-    return r <= kIluChainThreads && (r << lshift) <= (int64_t)kIluChainThreads * kIluChainCols;
-  };
-  int l = 0;
-  while (l < nlev) {
-    const int64_t r = rows_of(l);
-    if (!chainable(r)) {
-      const int64_t thr = r << lshift;
-      const int64_t g = std::min<int64_t>((thr + kIluThreads - 1) / kIluThreads, kIluMaxGrid);
-      plan.push_back({l, l + 1, (int)g, lshift, r, ents[l + 1] - ents[l]});
-      ++l;
-      continue;
-    }
-    int l1 = l;
-    int64_t maxr = 1;
-    while (l1 < nlev && chainable(rows_of(l1)) && l1 - l < kIluChainLevels) {
-      maxr = std::max(maxr, rows_of(l1));
-      ++l1;
-    }
-    int lsh = lshift;
-    if (!factor)
-      while (lsh > 0 && (maxr << lsh) > kIluChainThreads) --lsh;
-    plan.push_back({l, l1, 1, lsh, (int64_t)hptr[l1] - hptr[l], ents[l1] - ents[l]});
-    l = l1;
-  }
-  return plan;
-}
-
 template <typename T>
 std::string dev_alloc(IluFactors& f, T** p, int64_t count) {
   void* q = nullptr;
@@ -290,67 +244,10 @@ std::string dev_alloc(IluFactors& f, T** p, int64_t count) {
   return "";
 }
 
-// Host analysis of one sweep: levels, level order, entries per position, and
-// the map from each entry to its position in the sorted factor array.
-struct SweepHost {
-  std::vector<int> ptr, rows;
-  std::vector<int64_t> rp, map, pivmap, lents, emap;
-  std::vector<int> ci, ecol;
-};
-
-SweepHost analyse(int64_t n, const std::vector<int64_t>& srp, const std::vector<int>& sci,
-                  const std::vector<int64_t>& dg, bool lower) {
-  SweepHost h;
-  std::vector<int> lev(n, 0);
-  int nl = 0;
-  auto level_of = [&](int64_t i) {
-    int m = -1;
-    const int64_t a = lower ? srp[i] : dg[i] + 1, b = lower ? dg[i] : srp[i + 1];
-    for (int64_t p = a; p < b; ++p) m = std::max(m, lev[sci[p]]);
-    lev[i] = m + 1;
-    nl = std::max(nl, m + 2);
-  };
-  if (lower)
-    for (int64_t i = 0; i < n; ++i) level_of(i);
-  else
-    for (int64_t i = n - 1; i >= 0; --i) level_of(i);
-  h.ptr.assign(nl + 1, 0);
-  for (int64_t i = 0; i < n; ++i) h.ptr[lev[i] + 1] += 1;
-  for (int l = 0; l < nl; ++l) h.ptr[l + 1] += h.ptr[l];
-  std::vector<int> fill(h.ptr.begin(), h.ptr.end() - 1);
-  h.rows.resize(n);
-  for (int64_t i = 0; i < n; ++i) h.rows[fill[lev[i]]++] = (int)i;
-  h.rp.resize(n + 1);
-  h.rp[0] = 0;
-  h.pivmap.resize(lower ? 0 : n);
-  for (int64_t k = 0; k < n; ++k) {
-    const int64_t i = h.rows[k];
-    const int64_t a = lower ? srp[i] : dg[i] + 1, b = lower ? dg[i] : srp[i + 1];
-    for (int64_t p = a; p < b; ++p) {
-      h.ci.push_back(sci[p]);
-      h.map.push_back(p);
-    }
-    h.rp[k + 1] = h.rp[k] + (b - a);
-    if (!lower) h.pivmap[k] = dg[i];
-  }
-  h.lents.resize(nl + 1);
-  for (int l = 0; l <= nl; ++l) h.lents[l] = h.rp[h.ptr[l]];
-  // padded copy of each position's first kIluEll entries (map into the
-  // sweep's own entry array; -1: padding)
-  h.ecol.assign((size_t)n * kIluEll, 0);
-  h.emap.assign((size_t)n * kIluEll, -1);
-  for (int64_t k = 0; k < n; ++k)
-    for (int u = 0; u < kIluEll && h.rp[k] + u < h.rp[k + 1]; ++u) {
-      h.ecol[k * kIluEll + u] = h.ci[h.rp[k] + u];
-      h.emap[k * kIluEll + u] = h.rp[k] + u;
-    }
-  return h;
-}
-
 // Copy one sweep's schedule to the device: its arrays are allocated into
 // `keep` (the factors), the entry maps of the set-up into `tmp`.
 std::string upload(hipStream_t st, IluFactors& keep, IluFactors& tmp, int64_t n, IluSweep& sw,
-                   const SweepHost& h, bool lower, int64_t** map_dev, int64_t** pivmap_dev,
+                   const IluSweepHost& h, bool lower, int64_t** map_dev, int64_t** pivmap_dev,
                    int64_t** emap_dev) {
   std::string e;
   const int64_t ne = (int64_t)h.ci.size();
@@ -380,8 +277,8 @@ std::string upload(hipStream_t st, IluFactors& keep, IluFactors& tmp, int64_t n,
             cp(*emap_dev, h.emap.data(), sizeof(int64_t) * n * kIluEll);
   if (ok && !lower) ok = cp(*pivmap_dev, h.pivmap.data(), sizeof(int64_t) * n);
   if (!ok) return "copy of the ILU(0) level schedule failed";
-  for (int j = 0; j < 6; ++j) sw.plan[j] = make_plan(h.ptr, h.lents, j, false);
-  sw.fplan = make_plan(h.ptr, h.lents, 0, true);
+  for (int j = 0; j < 6; ++j) sw.plan[j] = ilu_make_plan(h.ptr, h.lents, j, false);
+  sw.fplan = ilu_make_plan(h.ptr, h.lents, 0, true);
   return "";
 }
 
@@ -438,27 +335,15 @@ std::string ilu_build(hipStream_t st, int64_t n, int64_t nnz, const int64_t* rp_
   // level positions and row indices are 32-bit
   if (n >= (int64_t)INT_MAX) return "ILU(0) needs n < 2^31 - 1";
   // rows with sorted columns; perm maps a sorted position to A's position
-  std::vector<int64_t> srp(rp_h, rp_h + n + 1), perm(nnz), dg(n, -1);
-  std::vector<int> sci(nnz);
-  std::vector<std::pair<int, int64_t>> row;
-  for (int64_t i = 0; i < n; ++i) {
-    row.clear();
-    for (int64_t p = rp_h[i]; p < rp_h[i + 1]; ++p) row.push_back({ci_h[p], p});
-    std::sort(row.begin(), row.end());
-    for (size_t q = 0; q < row.size(); ++q) {
-      const int64_t p = rp_h[i] + (int64_t)q;
-      sci[p] = row[q].first;
-      perm[p] = row[q].second;
-      if (q > 0 && row[q].first == row[q - 1].first)
-        return "row " + std::to_string(i) + " stores column " + std::to_string(row[q].first) +
-               " twice";
-      if (row[q].first == i) dg[i] = p;
-    }
-    if (dg[i] < 0) return "row " + std::to_string(i) + " stores no diagonal entry";
+  std::vector<int64_t> srp, perm, dg;
+  std::vector<int> sci;
+  {
+    const std::string e = ilu_sort_pattern(n, nnz, rp_h, ci_h, srp, sci, perm, dg);
+    if (!e.empty()) return e;
   }
   *bad_input = false;   // from here on, failures are the device's
-  const SweepHost lo = analyse(n, srp, sci, dg, true);
-  const SweepHost up = analyse(n, srp, sci, dg, false);
+  const IluSweepHost lo = ilu_analyse(n, srp, sci, dg, true);
+  const IluSweepHost up = ilu_analyse(n, srp, sci, dg, false);
   f.nnz_lo = (int64_t)lo.ci.size();
   f.nnz_up = (int64_t)up.ci.size();
   std::string e;

@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "ilu_plan.h"
 #include "lsba.h"
 
 namespace lsba {
@@ -284,13 +285,6 @@ void launch_house(hipStream_t st, const Dense& d, int64_t n, int s, const T* X, 
 // entries of position k (strictly lower part for the forward sweep, strictly
 // upper part for the backward sweep) are ci/v[rp[k] .. rp[k+1]), columns
 // ascending; piv[k] is u_ii (backward sweep only).
-constexpr int kIluEll = 4;
-struct IluLaunch {
-  int l0, l1;       // levels [l0, l1) of one launch
-  int grid;         // workgroups (1: the levels are chained in one workgroup)
-  int lsh;          // 2^lsh lanes per row
-  int64_t rows, ents;   // rows and off-diagonal entries the launch covers
-};
 struct IluSweep {
   int nlev = 0;
   int* lvl_ptr = nullptr;
